@@ -1,0 +1,184 @@
+/*
+ * eddy.h -- C ABI of the MI355X eddy-current A-V solver.
+ *
+ * Solves the time-harmonic, Coulomb-gauged A-V eddy-current system of
+ * Riahi, "A Fast Eddy-current Non Destructive Testing Finite Element Solver
+ * in Steam Generator": the model of Section 2 (Eq. 1), potentials
+ * E = i omega A + grad V, mu H = curl A (Eq. 2), the mixed sesquilinear form
+ * L of Eq. 7 with its blocks L11, L12, L21, L22, and the global block system
+ * of Section 3 with right-hand side (J_h ; 0).  A is discretised with
+ * lowest-order Nedelec (Whitney) edge elements, V with P1 on the nodes of
+ * the conducting sub-mesh:
+ *
+ *   M11 = K_nu + tau W D0^-1 W^T - i omega M_sigma      (A rows, A columns)
+ *   M12 = -B_sigma,  M21 = -B_sigma^T                     (A-V coupling)
+ *   M22 = (i / omega) S_sigma + delta_V N_sigma           (V rows, V columns)
+ *
+ * The div-div gauge term of Eqs. 5-7 vanishes on Whitney elements and is
+ * realised as the weak-divergence penalty tau W D0^-1 W^T, W = int w_e.grad l_n,
+ * D0 the lumped P1 mass.  The matrix is complex-symmetric.
+ *
+ * Conventions (every call):
+ *   - SI units; time factor e^{-i omega t} (Eq. 1).
+ *   - DOF order [A on edges ; V on conductor nodes].  Edges are the sorted
+ *     node pairs (lo, hi) in lexicographic order, oriented lo -> hi;
+ *     conductor nodes are in increasing global node id.
+ *   - Complex values are interleaved (re, im) doubles (eddy_c128).
+ *   - "dev" pointers are device (HBM) pointers owned by the caller; "host"
+ *     pointers are host memory owned by the caller.  Host inputs are copied
+ *     during the call.  The library never allocates device memory: every
+ *     device buffer comes from a caller-owned workspace whose size it
+ *     reports.  Handles own host metadata only.
+ *   - `stream` is a hipStream_t (0 = the null stream).  Calls that return
+ *     host data synchronise that stream; the others only enqueue work.
+ *   - Every call returns an eddy_status; negative = error (message in
+ *     eddy_last_error(), thread-local), positive = warning.  No call throws.
+ */
+#ifndef EDDY_H
+#define EDDY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EDDY_OK = 0,
+  EDDY_ERR_ARG = -1,             /* invalid argument or size                 */
+  EDDY_ERR_MESH = -2,            /* degenerate tetrahedron / bad indices     */
+  EDDY_ERR_WORKSPACE = -3,       /* workspace missing or too small           */
+  EDDY_ERR_DEVICE = -4,          /* HIP runtime error                        */
+  EDDY_ERR_SINGULAR_BLOCK = -5,  /* zero pivot in a preconditioner block     */
+  EDDY_WARN_NOT_CONVERGED = 1    /* solve hit max_iter; x holds the iterate  */
+} eddy_status;
+
+typedef struct { double re, im; } eddy_c128;
+typedef void* eddy_stream;                 /* hipStream_t */
+typedef struct eddy_mesh eddy_mesh;        /* opaque, host */
+typedef struct eddy_op eddy_op;            /* opaque, host metadata + workspace view */
+
+typedef struct {
+  double tau_gauge;    /* gauge penalty 1/mu~ (Eq. 3); > 0                        */
+  double delta_v;      /* optional V penalty delta*sigma*V (Section 4); >= 0      */
+  int32_t block_size;  /* block-Jacobi block size b, 1..64                         */
+} eddy_params;
+
+typedef struct {
+  double tol;          /* stop when ||D^-1/2 (b - M x)|| <= tol ||D^-1/2 b||      */
+  int32_t restart;     /* GMRES restart length m, 1..64                            */
+  int32_t max_iter;    /* total Arnoldi steps                                      */
+} eddy_solve_opts;
+
+typedef struct {
+  int32_t iters;       /* Arnoldi steps taken                                      */
+  int32_t restarts;    /* completed cycles                                         */
+  int32_t converged;   /* 1 if the true weighted residual met tol                  */
+  int32_t breakdown;   /* 1 if a happy breakdown ended a cycle                     */
+  double relres;       /* true weighted relative residual of the returned x        */
+  double est_relres;   /* Arnoldi estimate at exit                                 */
+  double seconds;      /* wall time of the call                                    */
+} eddy_solve_report;
+
+/* ---- mesh (host) -------------------------------------------------------
+ * eddy_mesh_create: nv nodes xyz[nv*3] (host, metres), nt tetrahedra
+ * tet[nt*4] (host, 0-based node ids, either orientation), region[nt]
+ * (host, 0..nreg-1), is_conductor[nreg] (host, nonzero = conducting region,
+ * i.e. sigma > 0 there; V lives on the nodes of those tetrahedra).  Builds
+ * edges, the CSR pattern of M and of W, scatter maps, conductor components.
+ * Errors: EDDY_ERR_ARG (sizes, indices), EDDY_ERR_MESH (|det| below
+ * 1e-12 * (longest edge)^3). */
+eddy_status eddy_mesh_create(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet,
+                             const int32_t* region, int32_t nreg, const int32_t* is_conductor,
+                             eddy_mesh** out);
+void eddy_mesh_destroy(eddy_mesh* mesh);
+/* Counts: edges, conductor nodes, nnz of the stored M (structural pattern of
+ * all element couplings, gauge excluded), nnz of W, conductor components. */
+eddy_status eddy_mesh_counts(const eddy_mesh* mesh, int64_t* ne, int64_t* nc, int64_t* nnz,
+                             int64_t* nnz_w, int32_t* ncomp);
+/* edge_nodes[ne*2] (host): (lo, hi) per edge.  cond_nodes[nc] (host). */
+eddy_status eddy_mesh_edges(const eddy_mesh* mesh, int32_t* edge_nodes);
+eddy_status eddy_mesh_conductor_nodes(const eddy_mesh* mesh, int32_t* cond_nodes);
+/* Block-Jacobi partition for block size b (recursive coordinate bisection of
+ * the DOF positions: edge midpoints and conductor nodes).  Call with
+ * block_ptr = block_dofs = NULL to get *nblocks; then block_ptr[nblocks+1]
+ * and block_dofs[ndof] (host) receive the blocks in order. */
+eddy_status eddy_mesh_blocks(const eddy_mesh* mesh, int32_t block_size, int64_t* nblocks,
+                             int32_t* block_ptr, int32_t* block_dofs);
+
+/* ---- operator ----------------------------------------------------------
+ * eddy_op_workspace_bytes: device bytes the operator needs for `params`.
+ * eddy_op_create: uploads mesh data and maps into dev_ws (device, >= bytes,
+ * 256-byte aligned, owned by the caller and kept alive until
+ * eddy_op_destroy).  The mesh may be destroyed afterwards. */
+eddy_status eddy_op_workspace_bytes(const eddy_mesh* mesh, const eddy_params* params, size_t* bytes);
+eddy_status eddy_op_create(const eddy_mesh* mesh, const eddy_params* params, void* dev_ws,
+                           size_t ws_bytes, eddy_stream stream, eddy_op** out);
+void eddy_op_destroy(eddy_op* op);
+/* Assemble M for nu[nreg] = 1/mu (host), sigma[nreg] (host, S/m; zero
+ * exactly on the non-conducting regions) and omega (rad/s): element kernel,
+ * deterministic scatter into CSR (no atomics), W and D0, symmetric
+ * equilibration D^-1/2 M D^-1/2 with D = |diag M|, then the dense inverses of
+ * the preconditioner's diagonal blocks (gauge included).  Reusable: call
+ * again for new materials or frequency.  Errors: EDDY_ERR_ARG,
+ * EDDY_ERR_SINGULAR_BLOCK (reported after synchronising). */
+eddy_status eddy_op_assemble(eddy_op* op, const double* nu, const double* sigma, double omega,
+                             eddy_stream stream);
+/* b[ndof] (dev) = [int J . w_e ; 0] for a current constant per tetrahedron,
+ * J_dev[nt*3] (dev, A/m^2): the source term of Eq. 5 (Section 3, right-hand side). */
+eddy_status eddy_rhs_from_current(const eddy_op* op, const double* J_dev, eddy_c128* b_dev,
+                                  eddy_stream stream);
+
+/* ---- solve -------------------------------------------------------------
+ * Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt
+ * applied twice (CGS2), block-Jacobi preconditioning, on the equilibrated
+ * system; x0 = 0.  b_dev[ndof] and x_dev[ndof] are device buffers (may not
+ * alias).  On return x holds [A ; V] with the mass-weighted mean of V removed
+ * per conductor component (Section 4).  ws: device workspace of at least
+ * eddy_solve_workspace_bytes.  rep (host) may be NULL. */
+eddy_status eddy_solve_workspace_bytes(const eddy_op* op, const eddy_solve_opts* opts, size_t* bytes);
+eddy_status eddy_solve(eddy_op* op, const eddy_c128* b_dev, eddy_c128* x_dev, const eddy_solve_opts* opts,
+                       void* ws, size_t ws_bytes, eddy_solve_report* rep, eddy_stream stream);
+
+/* ---- outputs -----------------------------------------------------------
+ * Coil impedance Z[k*nsrc + l] (host) = -(i omega / (I_k I_l)) b_l^T A_k for
+ * solutions x_dev[k*ndof ...] (k < nsol) and right-hand sides b_dev[l*ndof
+ * ...] (l < nsrc); currents[nsrc] (host, A).  Unconjugated product: the
+ * coils lie in the insulator, where E = i omega A (Eq. 2). */
+eddy_status eddy_impedance(const eddy_op* op, int32_t nsol, const eddy_c128* x_dev, int32_t nsrc,
+                           const eddy_c128* b_dev, const double* currents, eddy_c128* Z_host,
+                           eddy_stream stream);
+/* E_dev[ne] = i omega A_e + (V_hi - V_lo on edges of conducting tetrahedra):
+ * the edge degrees of freedom of E = i omega A + grad V (Eq. 2). */
+eddy_status eddy_edge_field(const eddy_op* op, const eddy_c128* x_dev, eddy_c128* E_dev, eddy_stream stream);
+
+/* ---- building blocks (parity tests and benchmarks) ---------------------
+ * y = M x with the gauge applied in factored form (unscaled system). */
+eddy_status eddy_spmv(const eddy_op* op, const eddy_c128* x_dev, eddy_c128* y_dev, eddy_stream stream);
+/* z = blockdiag(M)^-1 r over the block-Jacobi blocks (unscaled system). */
+eddy_status eddy_precond_apply(const eddy_op* op, const eddy_c128* r_dev, eddy_c128* z_dev, eddy_stream stream);
+/* Host copies of the stored (equilibrated) arrays: rowptr[ndof+1], col[nnz],
+ * val[nnz] = s_i M_ij s_j (gauge excluded), wval[nnz_w] = s_e W_en in the
+ * CSR order of W (rows = edges, columns = nodes, ascending), wrowptr[ne+1],
+ * wcol[nnz_w], d0[nv], s[ndof].  Any pointer may be NULL to skip it. */
+eddy_status eddy_export(const eddy_op* op, int32_t* rowptr, int32_t* col, eddy_c128* val,
+                        int32_t* wrowptr, int32_t* wcol, double* wval, double* d0, double* s,
+                        eddy_stream stream);
+
+/* Per-kernel-class timing of the GMRES loop, measured with HIP events on the
+ * solve's stream and read at the loop's per-iteration synchronisation.
+ * Classes: 0 block-Jacobi apply, 1 gauge product W~^T x, 2 CSR SpMV
+ * (+ W~ t), 3 CGS2 orthogonalisation + normalisation.  Returns (host) the
+ * accumulated milliseconds ms[4] and launch counts counts[4] since the
+ * previous call (either may be NULL), resets them, and turns timing on
+ * (enable != 0) or off.  Creating the events is the only allocation. */
+eddy_status eddy_profile(eddy_op* op, int32_t enable, double* ms, int64_t* counts);
+
+const char* eddy_status_string(eddy_status status);
+const char* eddy_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDDY_H */

@@ -1,0 +1,636 @@
+// C ABI of the eddy-current solver: mesh handle, operator workspace layout,
+// assembly sequence, the GMRES driver and the output calls.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace eddy {
+
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+#define HIP_TRY(expr)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));             \
+      return EDDY_ERR_DEVICE;                                                    \
+    }                                                                            \
+  } while (0)
+
+// Bump allocator over a caller-owned device range; a null base only measures.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(int64_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += sizeof(T) * (size_t)(count > 0 ? count : 0);
+    return p;
+  }
+};
+
+}  // namespace
+}  // namespace eddy
+
+using namespace eddy;
+
+struct eddy_op {
+  int64_t nv, nt, ne, nc, nct, n, nnz, nnzw, nb;
+  int32_t nreg, ncomp, bsize;
+  double tau, delta_v, omega = 0;
+  bool assembled = false;
+  // static (uploaded at create)
+  double* xyz;
+  int *tet, *region, *cidx, *edge_v, *comp;
+  uint8_t* signbits;
+  int *rowptr, *col, *diagpos, *cptr, *clist;
+  int *wrowptr, *wcol, *wcptr, *wclist, *wtrowptr, *wtcol, *wtperm;
+  int *d0ptr, *d0list, *lcptr, *lclist, *rptr, *rlist;
+  int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
+  // numeric
+  double2 *val, *ebuf, *minv;
+  double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *lumped, *s, *nu_reg, *sig_reg;
+  double2 *tmp1, *tmp2, *tvec, *red;
+  double* rred;
+  int* status;
+  size_t bytes;
+  // optional per-kernel-class timing of the GMRES loop (HIP events on the caller's stream)
+  bool profile = false;
+  hipEvent_t ev[10] = {};
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int64_t prof_n[5] = {0, 0, 0, 0, 0};
+  ~eddy_op() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+template <class T>
+size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
+  Carve c(base);
+  o->xyz = c.take<double>(m->nv * 3);
+  o->tet = c.take<int>(m->nt * 4);
+  o->region = c.take<int>(m->nt);
+  o->cidx = c.take<int>(m->nt);
+  o->signbits = c.take<uint8_t>(m->nt);
+  o->edge_v = c.take<int>(m->ne * 2);
+  o->comp = c.take<int>(m->nc);
+  o->rowptr = c.take<int>(m->ndof() + 1);
+  o->col = c.take<int>(m->nnz());
+  o->diagpos = c.take<int>(m->ndof());
+  o->cptr = c.take<int>(m->nnz() + 1);
+  o->clist = c.take<int>((int64_t)m->clist.size());
+  o->wrowptr = c.take<int>(m->ne + 1);
+  o->wcol = c.take<int>(m->nnzw());
+  o->wcptr = c.take<int>(m->nnzw() + 1);
+  o->wclist = c.take<int>((int64_t)m->wclist.size());
+  o->wtrowptr = c.take<int>(m->nv + 1);
+  o->wtcol = c.take<int>(m->nnzw());
+  o->wtperm = c.take<int>(m->nnzw());
+  o->d0ptr = c.take<int>(m->nv + 1);
+  o->d0list = c.take<int>((int64_t)m->d0list.size());
+  o->lcptr = c.take<int>(m->nc + 1);
+  o->lclist = c.take<int>((int64_t)m->lclist.size());
+  o->rptr = c.take<int>(m->ne + 1);
+  o->rlist = c.take<int>((int64_t)m->rlist.size());
+  const int64_t nb = (int64_t)m->blk_ptr.size() - 1;
+  o->blk_ptr = c.take<int>(nb + 1);
+  o->blk_dofs = c.take<int>(m->ndof());
+  o->blk_of = c.take<int>(m->ndof());
+  o->loc_of = c.take<int>(m->ndof());
+  o->val = c.take<double2>(m->nnz());
+  o->ebuf = c.take<double2>(21 * m->nt + 34 * m->nct);
+  o->minv = c.take<double2>(nb * kMaxBlock * kMaxBlock);
+  o->wval = c.take<double>(m->nnzw());
+  o->wtval = c.take<double>(m->nnzw());
+  o->wbuf = c.take<double>(24 * m->nt);
+  o->vol4 = c.take<double>(m->nt);
+  o->rbuf = c.take<double>(6 * m->nt);
+  o->d0 = c.take<double>(m->nv);
+  o->d0tau = c.take<double>(m->nv);
+  o->lumped = c.take<double>(m->nc);
+  o->s = c.take<double>(m->ndof());
+  o->nu_reg = c.take<double>(m->nreg);
+  o->sig_reg = c.take<double>(m->nreg);
+  o->tmp1 = c.take<double2>(m->ndof());
+  o->tmp2 = c.take<double2>(m->ndof());
+  o->tvec = c.take<double2>(m->nv);
+  o->red = c.take<double2>(kRedBlocks * (kMaxRestart + 1));
+  o->rred = c.take<double>(kRedBlocks + 8);
+  o->status = c.take<int>(4);
+  return c.off + 256;
+}
+
+eddy_status check_params(const eddy_params* p) {
+  if (!p) { set_error("params is NULL"); return EDDY_ERR_ARG; }
+  if (!(p->tau_gauge > 0)) { set_error("tau_gauge must be > 0"); return EDDY_ERR_ARG; }
+  if (!(p->delta_v >= 0)) { set_error("delta_v must be >= 0"); return EDDY_ERR_ARG; }
+  if (p->block_size < 1 || p->block_size > kMaxBlock) { set_error("block_size must be in 1..64"); return EDDY_ERR_ARG; }
+  return EDDY_OK;
+}
+
+template <class T>
+eddy_status upload(T* dst, const std::vector<T>& src, hipStream_t st) {
+  if (src.empty()) return EDDY_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, st));
+  return EDDY_OK;
+}
+
+// y = M~ x (scaled system); `t` is the node-sized gauge temporary.
+void op_spmv(const eddy_op* o, const double2* x, const double2* b, double2* y, double2* t, hipStream_t st) {
+  launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, x, t, st);
+  launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, o->wrowptr, o->wcol, o->wval, t, x, b, y, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* eddy_last_error(void) { return g_err.c_str(); }
+
+const char* eddy_status_string(eddy_status s) {
+  switch (s) {
+    case EDDY_OK: return "ok";
+    case EDDY_ERR_ARG: return "invalid argument";
+    case EDDY_ERR_MESH: return "invalid mesh";
+    case EDDY_ERR_WORKSPACE: return "workspace too small";
+    case EDDY_ERR_DEVICE: return "device error";
+    case EDDY_ERR_SINGULAR_BLOCK: return "singular preconditioner block";
+    case EDDY_WARN_NOT_CONVERGED: return "not converged";
+  }
+  return "unknown status";
+}
+
+eddy_status eddy_mesh_create(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet, const int32_t* region,
+                             int32_t nreg, const int32_t* is_conductor, eddy_mesh** out) {
+  if (!out || !xyz || !tet || !region || !is_conductor) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  *out = nullptr;
+  if (nv < 4 || nt < 1 || nreg < 1 || nv >= INT32_MAX || nt * 6 >= INT32_MAX) {
+    set_error("mesh sizes out of range");
+    return EDDY_ERR_ARG;
+  }
+  eddy_mesh* m = new (std::nothrow) eddy_mesh();
+  if (!m) { set_error("out of host memory"); return EDDY_ERR_ARG; }
+  try {
+    m->nv = nv;
+    m->nt = nt;
+    m->nreg = nreg;
+    m->xyz.assign(xyz, xyz + nv * 3);
+    m->tet.assign(tet, tet + nt * 4);
+    m->region.assign(region, region + nt);
+    m->is_cond.assign(is_conductor, is_conductor + nreg);
+    eddy_status st = build_mesh(m);
+    if (st != EDDY_OK) { delete m; return st; }
+  } catch (const std::exception& e) {
+    delete m;
+    set_error(std::string("host failure: ") + e.what());
+    return EDDY_ERR_ARG;
+  }
+  *out = m;
+  return EDDY_OK;
+}
+
+void eddy_mesh_destroy(eddy_mesh* m) { delete m; }
+
+eddy_status eddy_mesh_counts(const eddy_mesh* m, int64_t* ne, int64_t* nc, int64_t* nnz, int64_t* nnz_w,
+                             int32_t* ncomp) {
+  if (!m) { set_error("NULL mesh"); return EDDY_ERR_ARG; }
+  if (ne) *ne = m->ne;
+  if (nc) *nc = m->nc;
+  if (nnz) *nnz = m->nnz();
+  if (nnz_w) *nnz_w = m->nnzw();
+  if (ncomp) *ncomp = m->ncomp;
+  return EDDY_OK;
+}
+
+eddy_status eddy_mesh_edges(const eddy_mesh* m, int32_t* edge_nodes) {
+  if (!m || !edge_nodes) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  std::memcpy(edge_nodes, m->edges.data(), sizeof(int32_t) * m->edges.size());
+  return EDDY_OK;
+}
+
+eddy_status eddy_mesh_conductor_nodes(const eddy_mesh* m, int32_t* nodes) {
+  if (!m || !nodes) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  std::memcpy(nodes, m->cond_nodes.data(), sizeof(int32_t) * m->cond_nodes.size());
+  return EDDY_OK;
+}
+
+eddy_status eddy_mesh_blocks(const eddy_mesh* mc, int32_t b, int64_t* nblocks, int32_t* block_ptr,
+                             int32_t* block_dofs) {
+  if (!mc || !nblocks) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (b < 1 || b > kMaxBlock) { set_error("block_size must be in 1..64"); return EDDY_ERR_ARG; }
+  eddy_mesh* m = const_cast<eddy_mesh*>(mc);
+  eddy_status st = build_blocks(m, b);
+  if (st != EDDY_OK) return st;
+  *nblocks = (int64_t)m->blk_ptr.size() - 1;
+  if (block_ptr) std::memcpy(block_ptr, m->blk_ptr.data(), sizeof(int32_t) * m->blk_ptr.size());
+  if (block_dofs) std::memcpy(block_dofs, m->blk_dofs.data(), sizeof(int32_t) * m->blk_dofs.size());
+  return EDDY_OK;
+}
+
+eddy_status eddy_op_workspace_bytes(const eddy_mesh* mc, const eddy_params* p, size_t* bytes) {
+  if (!mc || !bytes) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  eddy_status st = check_params(p);
+  if (st != EDDY_OK) return st;
+  eddy_mesh* m = const_cast<eddy_mesh*>(mc);
+  st = build_blocks(m, p->block_size);
+  if (st != EDDY_OK) return st;
+  eddy_op tmp;
+  *bytes = carve_op(&tmp, (char*)nullptr, m);
+  return EDDY_OK;
+}
+
+eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_ws, size_t ws_bytes,
+                           eddy_stream stream, eddy_op** out) {
+  if (!mc || !out) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  *out = nullptr;
+  eddy_status st = check_params(p);
+  if (st != EDDY_OK) return st;
+  eddy_mesh* m = const_cast<eddy_mesh*>(mc);
+  st = build_blocks(m, p->block_size);
+  if (st != EDDY_OK) return st;
+  if (!dev_ws || ((uintptr_t)dev_ws & 255)) { set_error("workspace must be non-NULL and 256-byte aligned"); return EDDY_ERR_WORKSPACE; }
+  eddy_op* o = new (std::nothrow) eddy_op();
+  if (!o) { set_error("out of host memory"); return EDDY_ERR_ARG; }
+  const size_t need = carve_op(o, (char*)nullptr, m);
+  if (ws_bytes < need) {
+    delete o;
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return EDDY_ERR_WORKSPACE;
+  }
+  carve_op(o, (char*)dev_ws, m);
+  o->bytes = need;
+  o->nv = m->nv; o->nt = m->nt; o->ne = m->ne; o->nc = m->nc; o->nct = m->nct; o->n = m->ndof();
+  o->nnz = m->nnz(); o->nnzw = m->nnzw(); o->nb = (int64_t)m->blk_ptr.size() - 1;
+  o->nreg = m->nreg; o->ncomp = m->ncomp; o->bsize = p->block_size;
+  o->tau = p->tau_gauge; o->delta_v = p->delta_v;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> blk_of(o->n), loc_of(o->n);
+  for (int64_t k = 0; k < o->nb; ++k)
+    for (int32_t q = m->blk_ptr[k]; q < m->blk_ptr[k + 1]; ++q) {
+      blk_of[m->blk_dofs[q]] = (int32_t)k;
+      loc_of[m->blk_dofs[q]] = q - m->blk_ptr[k];
+    }
+  eddy_status r = EDDY_OK;
+#define UP(dst, src) if (r == EDDY_OK) r = upload(dst, src, s)
+  UP(o->xyz, m->xyz); UP(o->tet, m->tet); UP(o->region, m->region); UP(o->cidx, m->cidx);
+  UP(o->signbits, m->signbits); UP(o->edge_v, m->edge_v); UP(o->comp, m->comp);
+  UP(o->rowptr, m->rowptr); UP(o->col, m->col); UP(o->diagpos, m->diagpos); UP(o->cptr, m->cptr);
+  UP(o->clist, m->clist); UP(o->wrowptr, m->wrowptr); UP(o->wcol, m->wcol); UP(o->wcptr, m->wcptr);
+  UP(o->wclist, m->wclist); UP(o->wtrowptr, m->wtrowptr); UP(o->wtcol, m->wtcol); UP(o->wtperm, m->wtperm);
+  UP(o->d0ptr, m->d0ptr); UP(o->d0list, m->d0list); UP(o->lcptr, m->lcptr); UP(o->lclist, m->lclist);
+  UP(o->rptr, m->rptr); UP(o->rlist, m->rlist); UP(o->blk_ptr, m->blk_ptr); UP(o->blk_dofs, m->blk_dofs);
+  UP(o->blk_of, blk_of); UP(o->loc_of, loc_of);
+#undef UP
+  if (r == EDDY_OK) {
+    hipError_t e = hipStreamSynchronize(s);   // host vectors are freed after return
+    if (e != hipSuccess) { set_error(hipGetErrorString(e)); r = EDDY_ERR_DEVICE; }
+  }
+  if (r != EDDY_OK) { delete o; return r; }
+  *out = o;
+  return EDDY_OK;
+}
+
+void eddy_op_destroy(eddy_op* o) { delete o; }
+
+eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, double omega, eddy_stream stream) {
+  if (!o || !nu || !sigma) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (!(omega > 0)) { set_error("omega must be > 0"); return EDDY_ERR_ARG; }
+  for (int r = 0; r < o->nreg; ++r)
+    if (!(nu[r] > 0) || !(sigma[r] >= 0)) { set_error("nu must be > 0 and sigma >= 0"); return EDDY_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  o->omega = omega;
+  HIP_TRY(hipMemcpyAsync(o->nu_reg, nu, sizeof(double) * o->nreg, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(o->sig_reg, sigma, sizeof(double) * o->nreg, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(o->status, 0, sizeof(int) * 4, s));
+  launch_element(o->nt, o->nct, o->xyz, o->tet, o->region, o->signbits, o->cidx, o->nu_reg, o->sig_reg, omega,
+                 o->delta_v, o->ebuf, o->wbuf, o->vol4, s);
+  launch_gather_c(o->nnz, o->cptr, o->clist, o->ebuf, o->val, s);
+  launch_gather_r(o->nnzw, o->wcptr, o->wclist, o->wbuf, o->wval, s);
+  launch_gather_r(o->nv, o->d0ptr, o->d0list, o->vol4, o->d0, s);
+  launch_gather_r(o->nc, o->lcptr, o->lclist, o->vol4, o->lumped, s);
+  launch_d0tau(o->nv, o->d0, o->tau, o->d0tau, s);
+  launch_equilibrate(o->n, o->ne, o->diagpos, o->val, o->wrowptr, o->wcol, o->wval, o->d0tau, o->s, o->status, s);
+  launch_scale_rows(o->n, o->rowptr, o->col, o->val, o->s, s);
+  launch_scale_w(o->ne, o->wrowptr, o->wval, o->s, s);
+  launch_permute_r(o->nnzw, o->wtperm, o->wval, o->wtval, s);
+  launch_block_invert(o->nb, o->blk_ptr, o->blk_dofs, o->blk_of, o->loc_of, o->rowptr, o->col, o->val, o->ne,
+                      o->wrowptr, o->wcol, o->wval, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, o->minv, o->status, s);
+  HIP_TRY(hipGetLastError());
+  int stat = 0;
+  HIP_TRY(hipMemcpyAsync(&stat, o->status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stat & 2) { set_error("zero diagonal entry in M"); return EDDY_ERR_SINGULAR_BLOCK; }
+  if (stat & 1) { set_error("zero pivot in a block-Jacobi block"); return EDDY_ERR_SINGULAR_BLOCK; }
+  o->assembled = true;
+  return EDDY_OK;
+}
+
+eddy_status eddy_rhs_from_current(const eddy_op* o, const double* J, eddy_c128* b, eddy_stream stream) {
+  if (!o || !J || !b) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  launch_rhs_elem(o->nt, o->xyz, o->tet, o->signbits, J, o->rbuf, s);
+  launch_gather_r2c(o->ne, o->n, o->rptr, o->rlist, o->rbuf, (double2*)b, s);
+  HIP_TRY(hipGetLastError());
+  return EDDY_OK;
+}
+
+eddy_status eddy_spmv(const eddy_op* o, const eddy_c128* x, eddy_c128* y, eddy_stream stream) {
+  if (!o || !x || !y) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  // M = S^-1 M~ S^-1:  y = (M~ (x / s)) / s
+  launch_diag_scale(o->n, (const double2*)x, o->s, 1, o->tmp1, s);
+  op_spmv(o, o->tmp1, nullptr, o->tmp2, o->tvec, s);
+  launch_diag_scale(o->n, o->tmp2, o->s, 1, (double2*)y, s);
+  HIP_TRY(hipGetLastError());
+  return EDDY_OK;
+}
+
+eddy_status eddy_precond_apply(const eddy_op* o, const eddy_c128* r, eddy_c128* z, eddy_stream stream) {
+  if (!o || !r || !z) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  // blockdiag(M)^-1 = S blockdiag(M~)^-1 S
+  launch_diag_scale(o->n, (const double2*)r, o->s, 0, o->tmp1, s);
+  launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, o->tmp1, o->tmp2, s);
+  launch_diag_scale(o->n, o->tmp2, o->s, 0, (double2*)z, s);
+  HIP_TRY(hipGetLastError());
+  return EDDY_OK;
+}
+
+eddy_status eddy_export(const eddy_op* o, int32_t* rowptr, int32_t* col, eddy_c128* val, int32_t* wrowptr,
+                        int32_t* wcol, double* wval, double* d0, double* sc, eddy_stream stream) {
+  if (!o) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return dst ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
+  };
+  HIP_TRY(cp(rowptr, o->rowptr, sizeof(int) * (o->n + 1)));
+  HIP_TRY(cp(col, o->col, sizeof(int) * o->nnz));
+  HIP_TRY(cp(val, o->val, sizeof(double2) * o->nnz));
+  HIP_TRY(cp(wrowptr, o->wrowptr, sizeof(int) * (o->ne + 1)));
+  HIP_TRY(cp(wcol, o->wcol, sizeof(int) * o->nnzw));
+  HIP_TRY(cp(wval, o->wval, sizeof(double) * o->nnzw));
+  HIP_TRY(cp(d0, o->d0, sizeof(double) * o->nv));
+  HIP_TRY(cp(sc, o->s, sizeof(double) * o->n));
+  HIP_TRY(hipStreamSynchronize(s));
+  return EDDY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES
+// ---------------------------------------------------------------------------
+namespace {
+struct SolveWs {
+  double2 *V, *w, *z, *xt, *bt, *hd, *h1, *h2, *yd, *part;
+  double *rpart, *nrm;
+};
+size_t carve_solve(SolveWs* w, void* base, int64_t n, int m) {
+  Carve c(base);
+  w->V = c.take<double2>((int64_t)(m + 1) * n);
+  w->w = c.take<double2>(n);
+  w->z = c.take<double2>(n);
+  w->xt = c.take<double2>(n);
+  w->bt = c.take<double2>(n);
+  w->h1 = c.take<double2>(kMaxRestart + 2);
+  w->h2 = c.take<double2>(kMaxRestart + 2);
+  w->hd = c.take<double2>(kMaxRestart + 2);
+  w->yd = c.take<double2>(kMaxRestart + 2);
+  w->part = c.take<double2>((int64_t)kRedBlocks * (kMaxRestart + 2));
+  w->rpart = c.take<double>(kRedBlocks + 8);
+  w->nrm = c.take<double>(8);
+  return c.off + 256;
+}
+eddy_status check_opts(const eddy_solve_opts* p) {
+  if (!p) { set_error("opts is NULL"); return EDDY_ERR_ARG; }
+  if (p->restart < 1 || p->restart > kMaxRestart) { set_error("restart must be in 1..64"); return EDDY_ERR_ARG; }
+  if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return EDDY_ERR_ARG; }
+  if (!(p->tol > 0)) { set_error("tol must be > 0"); return EDDY_ERR_ARG; }
+  return EDDY_OK;
+}
+}  // namespace
+
+eddy_status eddy_solve_workspace_bytes(const eddy_op* o, const eddy_solve_opts* opts, size_t* bytes) {
+  if (!o || !bytes) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  eddy_status st = check_opts(opts);
+  if (st != EDDY_OK) return st;
+  SolveWs w;
+  *bytes = carve_solve(&w, nullptr, o->n, opts->restart);
+  return EDDY_OK;
+}
+
+eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, const eddy_solve_opts* opts, void* ws,
+                       size_t ws_bytes, eddy_solve_report* rep, eddy_stream stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!o || !b_dev || !x_dev) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+  eddy_status st = check_opts(opts);
+  if (st != EDDY_OK) return st;
+  const int m = opts->restart;
+  const int64_t n = o->n;
+  SolveWs W;
+  const size_t need = carve_solve(&W, nullptr, n, m);
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) {
+    set_error("solve workspace too small or misaligned: need " + std::to_string(need) + " bytes");
+    return EDDY_ERR_WORKSPACE;
+  }
+  carve_solve(&W, ws, n, m);
+  hipStream_t s = (hipStream_t)stream;
+  using cd = std::complex<double>;
+  double hbuf[8];
+  auto read_norm = [&](double* out) -> eddy_status {
+    HIP_TRY(hipMemcpyAsync(hbuf, W.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = hbuf[0];
+    return EDDY_OK;
+  };
+  // equilibrated right-hand side b~ = s b, x~ = 0
+  launch_diag_scale(n, (const double2*)b_dev, o->s, 0, W.bt, s);
+  launch_zero(n, W.xt, s);
+  launch_norm2(n, W.bt, W.rpart, W.nrm, s);
+  double bnorm = 0;
+  if ((st = read_norm(&bnorm)) != EDDY_OK) return st;
+  eddy_solve_report R{};
+  if (!std::isfinite(bnorm)) { set_error("right-hand side is not finite"); return EDDY_ERR_ARG; }
+  double beta = bnorm;
+  int it = 0;
+  std::vector<cd> H((m + 1) * m), g(m + 1), sn(m), y(m);
+  std::vector<double> cs(m);
+  std::vector<double2> hh1(m + 2), hh2(m + 2);
+  if (bnorm > 0) {
+    // r0 = b~ (x0 = 0)
+    const double2* r = W.bt;
+    while (true) {
+      launch_scale_host(n, r, 1.0 / beta, W.V, s);
+      std::fill(g.begin(), g.end(), cd(0));
+      g[0] = beta;
+      int k = 0;
+      bool stop = false;
+      for (int j = 0; j < m; ++j) {
+        double2* vj = W.V + (int64_t)j * n;
+        if (o->profile) (void)hipEventRecord(o->ev[0], s);
+        launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, vj, W.z, s);
+        if (o->profile) (void)hipEventRecord(o->ev[1], s);
+        launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, W.z, o->tvec, s);
+        if (o->profile) (void)hipEventRecord(o->ev[2], s);
+        launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, o->wrowptr, o->wcol, o->wval, o->tvec, W.z, nullptr, W.w,
+                    s);
+        if (o->profile) (void)hipEventRecord(o->ev[3], s);
+        // CGS2
+        launch_mdot(n, W.V, n, j + 1, W.w, W.part, s);
+        launch_reduce_cols(j + 1, W.part, W.h1, s);
+        launch_update(n, W.V, n, j + 1, W.h1, W.w, s);
+        launch_mdot(n, W.V, n, j + 1, W.w, W.part, s);
+        launch_reduce_cols(j + 1, W.part, W.h2, s);
+        launch_update(n, W.V, n, j + 1, W.h2, W.w, s);
+        launch_norm2(n, W.w, W.rpart, W.nrm, s);
+        launch_scale_by_inv(n, W.w, W.nrm, W.V + (int64_t)(j + 1) * n, s);
+        if (o->profile) (void)hipEventRecord(o->ev[4], s);
+        HIP_TRY(hipMemcpyAsync(hh1.data(), W.h1, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hh2.data(), W.h2, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hbuf, W.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (o->profile) {
+          for (int c = 0; c < 4; ++c) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, o->ev[c], o->ev[c + 1]) == hipSuccess) {
+              o->prof_ms[c] += ms;
+              o->prof_n[c] += 1;
+            }
+          }
+        }
+        const double hn = hbuf[0];
+        for (int i = 0; i <= j; ++i) H[i * m + j] = cd(hh1[i].x + hh2[i].x, hh1[i].y + hh2[i].y);
+        H[(j + 1) * m + j] = hn;
+        for (int i = 0; i < j; ++i) {
+          cd a = H[i * m + j], bb = H[(i + 1) * m + j];
+          H[i * m + j] = cs[i] * a + sn[i] * bb;
+          H[(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bb;
+        }
+        cd a = H[j * m + j];
+        const double bb = hn;
+        double c;
+        cd sv, rr;
+        if (bb == 0.0) { c = 1.0; sv = 0.0; rr = a; }
+        else if (std::abs(a) == 0.0) { c = 0.0; sv = 1.0; rr = bb; }
+        else {
+          const double t = std::hypot(std::abs(a), bb);
+          c = std::abs(a) / t;
+          sv = (a / std::abs(a)) * bb / t;
+          rr = (a / std::abs(a)) * t;
+        }
+        cs[j] = c;
+        sn[j] = sv;
+        H[j * m + j] = rr;
+        H[(j + 1) * m + j] = 0.0;
+        g[j + 1] = -std::conj(sv) * g[j];
+        g[j] = c * g[j];
+        ++it;
+        k = j + 1;
+        R.est_relres = std::abs(g[j + 1]) / bnorm;
+        if (!std::isfinite(R.est_relres)) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
+        if (hn == 0.0) R.breakdown = 1;
+        if (R.est_relres <= opts->tol || it >= opts->max_iter || hn == 0.0) { stop = true; break; }
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        cd acc = g[i];
+        for (int l = i + 1; l < k; ++l) acc -= H[i * m + l] * y[l];
+        y[i] = acc / H[i * m + i];
+      }
+      std::vector<double2> yv(k);
+      for (int i = 0; i < k; ++i) yv[i] = make_double2(y[i].real(), y[i].imag());
+      HIP_TRY(hipMemcpyAsync(W.yd, yv.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
+      launch_combine(n, W.V, n, k, W.yd, W.w, s);
+      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, W.w, W.z, s);
+      launch_axpy(n, W.z, W.xt, s);
+      // true residual r = b~ - M~ x~
+      op_spmv(o, W.xt, W.bt, W.w, o->tvec, s);
+      launch_norm2(n, W.w, W.rpart, W.nrm, s);
+      if ((st = read_norm(&beta)) != EDDY_OK) return st;
+      HIP_TRY(hipStreamSynchronize(s));   // yv must outlive its copy
+      R.restarts++;
+      R.relres = beta / bnorm;
+      if (R.relres <= opts->tol || it >= opts->max_iter) break;
+      if (stop && R.breakdown) break;
+      r = W.w;
+    }
+  } else {
+    R.relres = 0;
+  }
+  // x = s x~, then remove the mass-weighted V mean per conductor component
+  launch_diag_scale(n, W.xt, o->s, 0, (double2*)x_dev, s);
+  launch_vmean(o->nc, o->ncomp, o->comp, o->lumped, (double2*)x_dev + o->ne, o->red, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  R.iters = it;
+  R.converged = R.relres <= opts->tol ? 1 : 0;
+  R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = R;
+  return R.converged ? EDDY_OK : EDDY_WARN_NOT_CONVERGED;
+}
+
+eddy_status eddy_profile(eddy_op* o, int32_t enable, double* ms, int64_t* counts) {
+  if (!o) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (ms)
+    for (int c = 0; c < 4; ++c) ms[c] = o->prof_ms[c];
+  if (counts)
+    for (int c = 0; c < 4; ++c) counts[c] = o->prof_n[c];
+  for (int c = 0; c < 5; ++c) o->prof_ms[c] = 0, o->prof_n[c] = 0;
+  if (enable && !o->ev[0])
+    for (auto& e : o->ev) HIP_TRY(hipEventCreate(&e));
+  o->profile = enable != 0;
+  return EDDY_OK;
+}
+
+eddy_status eddy_impedance(const eddy_op* o, int32_t nsol, const eddy_c128* x_dev, int32_t nsrc,
+                           const eddy_c128* b_dev, const double* currents, eddy_c128* Z, eddy_stream stream) {
+  if (!o || !x_dev || !b_dev || !currents || !Z || nsol < 1 || nsrc < 1 || nsol > nsrc || (int64_t)nsol * nsrc > o->n) {
+    set_error("bad argument (need 1 <= nsol <= nsrc, NULL pointers?)");
+    return EDDY_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double2> dots((size_t)nsol * nsrc);
+  for (int k = 0; k < nsol; ++k)
+    for (int l = 0; l < nsrc; ++l) {
+      launch_udot(o->ne, (const double2*)b_dev + (int64_t)l * o->n, (const double2*)x_dev + (int64_t)k * o->n, o->red,
+                  o->tmp1 + (k * nsrc + l), s);
+    }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(dots.data(), o->tmp1, sizeof(double2) * dots.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < nsol; ++k)
+    for (int l = 0; l < nsrc; ++l) {
+      const std::complex<double> d(dots[k * nsrc + l].x, dots[k * nsrc + l].y);
+      const std::complex<double> z = std::complex<double>(0, -o->omega) / (currents[k] * currents[l]) * d;
+      Z[k * nsrc + l].re = z.real();
+      Z[k * nsrc + l].im = z.imag();
+    }
+  return EDDY_OK;
+}
+
+eddy_status eddy_edge_field(const eddy_op* o, const eddy_c128* x, eddy_c128* E, eddy_stream stream) {
+  if (!o || !x || !E) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  launch_edge_field(o->ne, o->edge_v, (const double2*)x, o->omega, (double2*)E, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return EDDY_OK;
+}
+
+}  // extern "C"

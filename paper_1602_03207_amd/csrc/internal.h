@@ -1,0 +1,80 @@
+// Internal definitions shared by the host mesh code, the API layer and the
+// HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "eddy.h"
+
+// ---------------------------------------------------------------------------
+// Element-buffer layout: the element kernel writes every element-level value
+// exactly once at these positions; the scatter maps built on the host refer
+// to them.  Local edges of a tetrahedron are (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+//
+//   ebuf (complex):  AA  pair slot p (0..20) of the 6x6 A-A block: p*nt + t
+//                    AV  (l*4 + k) of the 6x4 A-V block:           AV0 + (l*4+k)*nct + c
+//                    VV  pair slot q (0..9) of the 4x4 V-V block:  VV0 + q*nct + c
+//   wbuf (real):     W_e (l*4 + k):                                 (l*4+k)*nt + t
+//   vol4 (real):     |K| / 4:                                       t
+//   rbuf (real):     int J . w_l:                                   l*nt + t
+// with t the tetrahedron, c its compact conductor index (nct of them).
+// ---------------------------------------------------------------------------
+namespace eddy {
+
+constexpr int kLocalEdge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+constexpr int kMaxBlock = 64;       // block-Jacobi block size limit (LDS-resident inverse)
+constexpr int kMaxRestart = 64;
+
+inline int pair6(int l, int m) {    // upper-triangle slot of a symmetric 6x6
+  if (l > m) { int t = l; l = m; m = t; }
+  return l * 6 - (l * (l - 1)) / 2 + (m - l);
+}
+inline int pair4(int i, int j) {    // upper-triangle slot of a symmetric 4x4
+  if (i > j) { int t = i; i = j; j = t; }
+  return i * 4 - (i * (i - 1)) / 2 + (j - i);
+}
+
+void set_error(const std::string& msg);
+
+}  // namespace eddy
+
+struct eddy_mesh {
+  int64_t nv = 0, nt = 0;
+  int32_t nreg = 0;
+  std::vector<double> xyz;          // nv*3
+  std::vector<int32_t> tet;         // nt*4
+  std::vector<int32_t> region;      // nt
+  std::vector<int32_t> is_cond;     // nreg
+  // topology
+  int64_t ne = 0, nc = 0, nct = 0;
+  int32_t ncomp = 0;
+  std::vector<int32_t> edges;       // ne*2 (lo, hi)
+  std::vector<int32_t> tet2edge;    // nt*6
+  std::vector<uint8_t> signbits;    // nt; bit l set if local edge l runs hi -> lo
+  std::vector<int32_t> cidx;        // nt; compact conductor index or -1
+  std::vector<int32_t> cond_nodes;  // nc
+  std::vector<int32_t> vmap;        // nv; conductor index or -1
+  std::vector<int32_t> comp;        // nc; conductor component
+  std::vector<int32_t> edge_v;      // ne*2; conductor ids of (lo, hi) on conducting edges, else -1
+  // M: structural CSR pattern and scatter lists into ebuf
+  std::vector<int32_t> rowptr, col, diagpos, cptr, clist;
+  // W (ne x nv): pattern and scatter lists into wbuf; W^T via a permutation
+  std::vector<int32_t> wrowptr, wcol, wcptr, wclist;
+  std::vector<int32_t> wtrowptr, wtcol, wtperm;
+  // gathers of vol4 (D0 over all tets, lumped conductor mass) and of rbuf
+  std::vector<int32_t> d0ptr, d0list, lcptr, lclist, rptr, rlist;
+  // cached block partition
+  int32_t blk_b = 0;
+  std::vector<int32_t> blk_ptr, blk_dofs;
+
+  int64_t ndof() const { return ne + nc; }
+  int64_t nnz() const { return (int64_t)col.size(); }
+  int64_t nnzw() const { return (int64_t)wcol.size(); }
+};
+
+namespace eddy {
+eddy_status build_mesh(eddy_mesh* m);                  // topology + patterns + maps
+eddy_status build_blocks(eddy_mesh* m, int32_t b);     // RCB partition (cached)
+}  // namespace eddy

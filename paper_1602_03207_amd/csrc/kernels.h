@@ -1,0 +1,59 @@
+// Launch wrappers for the HIP kernels (kernels.hip).  All complex vectors are
+// double2 (re, im); all launches are asynchronous on `st`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace eddy {
+
+constexpr int kRedBlocks = 512;       // blocks of the two-stage reductions
+
+// ---- assembly (Section 2, Eqs. 5-7; Section 3 global blocks)
+void launch_element(int64_t nt, int64_t nct, const double* xyz, const int* tet, const int* region,
+                    const uint8_t* signbits, const int* cidx, const double* nu_reg, const double* sig_reg,
+                    double omega, double delta_v, double2* ebuf, double* wbuf, double* vol4, hipStream_t st);
+void launch_gather_c(int64_t n, const int* ptr, const int* list, const double2* buf, double2* out, hipStream_t st);
+void launch_gather_r(int64_t n, const int* ptr, const int* list, const double* buf, double* out, hipStream_t st);
+void launch_gather_r2c(int64_t n, int64_t ntot, const int* ptr, const int* list, const double* buf, double2* out,
+                       hipStream_t st);
+void launch_permute_r(int64_t n, const int* perm, const double* in, double* out, hipStream_t st);
+void launch_d0tau(int64_t nv, const double* d0, double tau, double* d0tau, hipStream_t st);
+void launch_equilibrate(int64_t n, int64_t ne, const int* diagpos, const double2* val, const int* wrowptr,
+                        const int* wcol, const double* wval, const double* d0tau, double* s, int* status,
+                        hipStream_t st);
+void launch_scale_rows(int64_t n, const int* rowptr, const int* col, double2* val, const double* s, hipStream_t st);
+void launch_scale_w(int64_t ne, const int* wrowptr, double* wval, const double* s, hipStream_t st);
+void launch_block_invert(int64_t nb, const int* blk_ptr, const int* blk_dofs, const int* blk_of, const int* loc_of,
+                         const int* rowptr, const int* col, const double2* val, int64_t ne, const int* wrowptr,
+                         const int* wcol, const double* wval, const int* wtrowptr, const int* wtcol,
+                         const double* wtval, const double* d0tau, double2* minv, int* status, hipStream_t st);
+void launch_rhs_elem(int64_t nt, const double* xyz, const int* tet, const uint8_t* signbits, const double* J,
+                     double* rbuf, hipStream_t st);
+
+// ---- solve
+void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const double* d0tau,
+               const double2* x, double2* t, hipStream_t st);
+// y = M~ x + W~ t  (A rows); if b != nullptr: y = b - (...)
+void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const double2* val, const int* wrowptr,
+                 const int* wcol, const double* wval, const double2* t, const double2* x, const double2* b,
+                 double2* y, hipStream_t st);
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const double2* minv, const double2* r,
+                        double2* z, hipStream_t st);
+void launch_mdot(int64_t n, const double2* V, int64_t ldv, int q, const double2* w, double2* partial, hipStream_t st);
+void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st);
+void launch_update(int64_t n, const double2* V, int64_t ldv, int q, const double2* h, double2* w, hipStream_t st);
+void launch_norm2(int64_t n, const double2* w, double* partial, double* out_norm, hipStream_t st);
+void launch_scale_by_inv(int64_t n, const double2* w, const double* norm, double2* v, hipStream_t st);
+void launch_scale_host(int64_t n, const double2* w, double a, double2* v, hipStream_t st);
+void launch_combine(int64_t n, const double2* V, int64_t ldv, int q, const double2* y, double2* u, hipStream_t st);
+void launch_axpy(int64_t n, const double2* z, double2* x, hipStream_t st);
+void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st);
+void launch_zero(int64_t n, double2* x, hipStream_t st);
+void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, double2* V, double2* scratch,
+                  hipStream_t st);
+void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st);
+void launch_edge_field(int64_t ne, const int* edge_v, const double2* x, double omega, double2* E, hipStream_t st);
+
+}  // namespace eddy

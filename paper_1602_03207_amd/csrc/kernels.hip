@@ -1,0 +1,749 @@
+// HIP kernels of the A-V eddy-current solver, written for gfx950 (CDNA4,
+// 64-wide wavefronts).  Every reduction runs in a fixed order, so results are
+// bitwise reproducible run to run; assembly uses no atomics.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace eddy {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + conj(a) * b
+__device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) {
+  return make_double2(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y)));
+}
+// acc + a * b
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+// acc + r * b (r real)
+__device__ __forceinline__ double2 rfma(double r, double2 b, double2 acc) {
+  return make_double2(fma(r, b.x, acc.x), fma(r, b.y, acc.y));
+}
+
+inline unsigned blocks_for(int64_t n, int per = kThreads) {
+  int64_t b = (n + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Deterministic sum over a 256-thread block (fixed shuffle tree, then the 4
+// wave totals in order).  Result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Element kernel: one thread per tetrahedron.  grad(l_1..3) are the columns
+// of E^-1 (E has rows p_i - p_0), obtained from cross products of the rows;
+// grad(l_0) = -sum.  For local edges l = (a, b), m = (c, d):
+//   K_lm = |K| curl w_l . curl w_m,      curl w_l = 2 grad l_a x grad l_b
+//   M_lm = |K|/20 [(1+d_ac) G_bd - (1+d_ad) G_bc - (1+d_bc) G_ad + (1+d_bd) G_ac]
+//   W_lk = |K|/4 (grad l_b - grad l_a) . grad l_k
+//   S_ij = |K| G_ij,  N_ij = |K| (1 + d_ij) / 20,   G_ij = grad l_i . grad l_j
+// Stored (global orientation signs s applied):
+//   AA = s_l s_m (nu K_lm - i omega sigma M_lm)        (M11 without gauge)
+//   AV = -sigma W_lk                                    (M12 = -B_sigma)
+//   VV = delta_V sigma N_ij + i sigma S_ij / omega      (M22)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_element(int64_t nt, int64_t nct, const double* __restrict__ xyz,
+                                                      const int* __restrict__ tet, const int* __restrict__ region,
+                                                      const uint8_t* __restrict__ signbits,
+                                                      const int* __restrict__ cidx, const double* __restrict__ nu_reg,
+                                                      const double* __restrict__ sig_reg, double omega, double delta_v,
+                                                      double2* __restrict__ ebuf, double* __restrict__ wbuf,
+                                                      double* __restrict__ vol4) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int4 nd = reinterpret_cast<const int4*>(tet)[t];
+  const int n[4] = {nd.x, nd.y, nd.z, nd.w};
+  double p[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) p[k][j] = xyz[3 * (int64_t)n[k] + j];
+  double e1[3], e2[3], e3[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    e1[j] = p[1][j] - p[0][j];
+    e2[j] = p[2][j] - p[0][j];
+    e3[j] = p[3][j] - p[0][j];
+  }
+  double c23[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2], e2[0] * e3[1] - e2[1] * e3[0]};
+  double c31[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2], e3[0] * e1[1] - e3[1] * e1[0]};
+  double c12[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
+  const double id = 1.0 / det;
+  const double vol = fabs(det) * (1.0 / 6.0);
+  double g[4][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    g[1][j] = c23[j] * id;
+    g[2][j] = c31[j] * id;
+    g[3][j] = c12[j] * id;
+    g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
+  }
+  double G[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) G[i][k] = g[i][0] * g[k][0] + g[i][1] * g[k][1] + g[i][2] * g[k][2];
+  constexpr int ea[6] = {0, 0, 0, 1, 1, 2};
+  constexpr int eb[6] = {1, 2, 3, 2, 3, 3};
+  const uint8_t sb = signbits[t];
+  double sg[6], cu[6][3];
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    sg[l] = ((sb >> l) & 1) ? -1.0 : 1.0;
+    const double* a = g[ea[l]];
+    const double* b = g[eb[l]];
+    cu[l][0] = 2.0 * (a[1] * b[2] - a[2] * b[1]);
+    cu[l][1] = 2.0 * (a[2] * b[0] - a[0] * b[2]);
+    cu[l][2] = 2.0 * (a[0] * b[1] - a[1] * b[0]);
+  }
+  const int reg = region[t];
+  const double nu = nu_reg[reg], sig = sig_reg[reg];
+  const double v20 = vol * (1.0 / 20.0);
+  int slot = 0;
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+#pragma unroll
+    for (int m = l; m < 6; ++m) {
+      const int a = ea[l], b = eb[l], c = ea[m], d = eb[m];
+      const double K = vol * (cu[l][0] * cu[m][0] + cu[l][1] * cu[m][1] + cu[l][2] * cu[m][2]);
+      const double M = v20 * ((a == c ? 2.0 : 1.0) * G[b][d] - (a == d ? 2.0 : 1.0) * G[b][c] -
+                              (b == c ? 2.0 : 1.0) * G[a][d] + (b == d ? 2.0 : 1.0) * G[a][c]);
+      const double ss = sg[l] * sg[m];
+      ebuf[(int64_t)slot * nt + t] = make_double2(ss * nu * K, -ss * omega * sig * M);
+      ++slot;
+    }
+  }
+  double Wl[6][4];
+  const double v4 = vol * 0.25;
+#pragma unroll
+  for (int l = 0; l < 6; ++l)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Wl[l][k] = sg[l] * v4 * (G[eb[l]][k] - G[ea[l]][k]);
+      wbuf[(int64_t)(l * 4 + k) * nt + t] = Wl[l][k];
+    }
+  vol4[t] = v4;
+  const int c = cidx[t];
+  if (c >= 0) {
+    const int64_t av0 = 21 * nt, vv0 = 21 * nt + 24 * nct;
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ebuf[av0 + (int64_t)(l * 4 + k) * nct + c] = make_double2(-sig * Wl[l][k], 0.0);
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i; j < 4; ++j) {
+        const double N = v20 * (i == j ? 2.0 : 1.0);
+        ebuf[vv0 + (int64_t)q * nct + c] = make_double2(delta_v * sig * N, sig * vol * G[i][j] / omega);
+        ++q;
+      }
+  }
+}
+
+// out[i] = sum of buf[list[p]] for p in [ptr[i], ptr[i+1]), in list order.
+__global__ __launch_bounds__(kThreads) void k_gather_c(int64_t n, const int* __restrict__ ptr,
+                                                       const int* __restrict__ list, const double2* __restrict__ buf,
+                                                       double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int p = ptr[i]; p < ptr[i + 1]; ++p) s = cadd(s, buf[list[p]]);
+  out[i] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather_r(int64_t n, const int* __restrict__ ptr,
+                                                       const int* __restrict__ list, const double* __restrict__ buf,
+                                                       double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int p = ptr[i]; p < ptr[i + 1]; ++p) s += buf[list[p]];
+  out[i] = s;
+}
+
+// rows < n gather real sums into complex outputs; rows n..ntot-1 are zeroed
+__global__ __launch_bounds__(kThreads) void k_gather_r2c(int64_t n, int64_t ntot, const int* __restrict__ ptr,
+                                                         const int* __restrict__ list, const double* __restrict__ buf,
+                                                         double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  double s = 0.0;
+  if (i < n)
+    for (int p = ptr[i]; p < ptr[i + 1]; ++p) s += buf[list[p]];
+  out[i] = make_double2(s, 0.0);
+}
+
+__global__ __launch_bounds__(kThreads) void k_permute_r(int64_t n, const int* __restrict__ perm,
+                                                        const double* __restrict__ in, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[perm[i]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_d0tau(int64_t nv, const double* __restrict__ d0, double tau,
+                                                    double* __restrict__ d0tau) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nv) d0tau[i] = tau / d0[i];
+}
+
+// s_i = |M_ii|^-1/2 with the gauge diagonal tau sum_n W_in^2 / D0_n on A rows.
+__global__ __launch_bounds__(kThreads) void k_equilibrate(int64_t n, int64_t ne, const int* __restrict__ diagpos,
+                                                          const double2* __restrict__ val,
+                                                          const int* __restrict__ wrowptr,
+                                                          const int* __restrict__ wcol,
+                                                          const double* __restrict__ wval,
+                                                          const double* __restrict__ d0tau, double* __restrict__ s,
+                                                          int* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 d = val[diagpos[i]];
+  if (i < ne) {
+    double gsum = 0.0;
+    for (int p = wrowptr[i]; p < wrowptr[i + 1]; ++p) gsum += wval[p] * wval[p] * d0tau[wcol[p]];
+    d.x += gsum;
+  }
+  const double a = sqrt(d.x * d.x + d.y * d.y);
+  if (!(a > 0.0)) {
+    atomicOr(status, 2);
+    s[i] = 1.0;
+  } else {
+    s[i] = 1.0 / sqrt(a);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_rows(int64_t n, const int* __restrict__ rowptr,
+                                                         const int* __restrict__ col, double2* __restrict__ val,
+                                                         const double* __restrict__ s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double si = s[i];
+  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    const double f = si * s[col[p]];
+    double2 v = val[p];
+    val[p] = make_double2(v.x * f, v.y * f);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_w(int64_t ne, const int* __restrict__ wrowptr,
+                                                      double* __restrict__ wval, const double* __restrict__ s) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double se = s[e];
+  for (int p = wrowptr[e]; p < wrowptr[e + 1]; ++p) wval[p] *= se;
+}
+
+// ---------------------------------------------------------------------------
+// Dense inverse of one equilibrated diagonal block per 64-thread workgroup:
+// gather the block (CSR part + factored gauge part) into LDS column-major,
+// Gauss-Jordan with partial pivoting (thread i owns row i; thread j owns
+// column j for row swaps), undo the column permutation, store column-major.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kMaxBlock) void k_block_invert(
+    const int* __restrict__ blk_ptr, const int* __restrict__ blk_dofs, const int* __restrict__ blk_of,
+    const int* __restrict__ loc_of, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const double2* __restrict__ val, int64_t ne, const int* __restrict__ wrowptr, const int* __restrict__ wcol,
+    const double* __restrict__ wval, const int* __restrict__ wtrowptr, const int* __restrict__ wtcol,
+    const double* __restrict__ wtval, const double* __restrict__ d0tau, double2* __restrict__ minv,
+    int* __restrict__ status) {
+  __shared__ double2 A[kMaxBlock * kMaxBlock];   // A(i, j) at j * 64 + i
+  __shared__ int perm[kMaxBlock];
+  const int k = blockIdx.x;
+  const int i = threadIdx.x;
+  const int b0 = blk_ptr[k];
+  const int sz = blk_ptr[k + 1] - b0;
+  for (int j = 0; j < kMaxBlock; ++j) A[j * kMaxBlock + i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (i < sz) {
+    const int r = blk_dofs[b0 + i];
+    for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+      const int c = col[p];
+      if (blk_of[c] == k) A[loc_of[c] * kMaxBlock + i] = val[p];
+    }
+    if (r < ne) {
+      for (int p = wrowptr[r]; p < wrowptr[r + 1]; ++p) {
+        const int nn = wcol[p];
+        const double f = wval[p] * d0tau[nn];
+        for (int q = wtrowptr[nn]; q < wtrowptr[nn + 1]; ++q) {
+          const int c = wtcol[q];
+          if (blk_of[c] == k) A[loc_of[c] * kMaxBlock + i].x += f * wtval[q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int kk = 0; kk < sz; ++kk) {
+    // pivot: largest |A(i, kk)| over i >= kk, lowest row on ties
+    double2 a = A[kk * kMaxBlock + i];
+    double mag = (i >= kk && i < sz) ? a.x * a.x + a.y * a.y : -1.0;
+    int arg = i;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double om = __shfl_xor(mag, o, 64);
+      const int oa = __shfl_xor(arg, o, 64);
+      if (om > mag || (om == mag && oa < arg)) {
+        mag = om;
+        arg = oa;
+      }
+    }
+    const int piv = __shfl(arg, 0, 64);
+    const double pmag = __shfl(mag, 0, 64);
+    if (i == 0) perm[kk] = piv;
+    if (!(pmag > 0.0)) {
+      if (i == 0) atomicOr(status, 1);
+      return;   // uniform across the workgroup
+    }
+    if (piv != kk) {   // swap rows kk and piv; thread i owns column i
+      const double2 t0 = A[i * kMaxBlock + kk];
+      A[i * kMaxBlock + kk] = A[i * kMaxBlock + piv];
+      A[i * kMaxBlock + piv] = t0;
+    }
+    __syncthreads();
+    const double2 pv = A[kk * kMaxBlock + kk];
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    const double2 inv = make_double2(pv.x / den, -pv.y / den);
+    __syncthreads();
+    // scale row kk (thread i owns column i); A(kk, kk) becomes 1 / pivot
+    if (i < sz) A[i * kMaxBlock + kk] = (i == kk) ? inv : cmul(A[i * kMaxBlock + kk], inv);
+    __syncthreads();
+    if (i < sz && i != kk) {
+      const double2 f = A[kk * kMaxBlock + i];
+      A[kk * kMaxBlock + i] = make_double2(0.0, 0.0);
+      for (int j = 0; j < sz; ++j) {
+        const double2 rk = A[j * kMaxBlock + kk];
+        A[j * kMaxBlock + i] = csub(A[j * kMaxBlock + i], cmul(f, rk));
+      }
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges on the columns, last first (thread i owns row i)
+  for (int kk = sz - 1; kk >= 0; --kk) {
+    const int p = perm[kk];
+    if (p != kk && i < sz) {
+      const double2 t0 = A[kk * kMaxBlock + i];
+      A[kk * kMaxBlock + i] = A[p * kMaxBlock + i];
+      A[p * kMaxBlock + i] = t0;
+    }
+  }
+  __syncthreads();
+  double2* out = minv + (int64_t)k * kMaxBlock * kMaxBlock;
+  for (int j = 0; j < sz; ++j) out[j * kMaxBlock + i] = A[j * kMaxBlock + i];
+}
+
+// rbuf[l*nt + t] = s_l J_t . |K|/4 (grad l_b - grad l_a)   (int J . w_l)
+__global__ __launch_bounds__(kThreads) void k_rhs_elem(int64_t nt, const double* __restrict__ xyz,
+                                                       const int* __restrict__ tet,
+                                                       const uint8_t* __restrict__ signbits,
+                                                       const double* __restrict__ J, double* __restrict__ rbuf) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int4 nd = reinterpret_cast<const int4*>(tet)[t];
+  const int n[4] = {nd.x, nd.y, nd.z, nd.w};
+  double p[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) p[k][j] = xyz[3 * (int64_t)n[k] + j];
+  double e1[3], e2[3], e3[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    e1[j] = p[1][j] - p[0][j];
+    e2[j] = p[2][j] - p[0][j];
+    e3[j] = p[3][j] - p[0][j];
+  }
+  const double c23[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2], e2[0] * e3[1] - e2[1] * e3[0]};
+  const double c31[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2], e3[0] * e1[1] - e3[1] * e1[0]};
+  const double c12[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
+  const double v4 = fabs(det) * (1.0 / 24.0);
+  const double id = 1.0 / det;
+  const double Jx = J[3 * t], Jy = J[3 * t + 1], Jz = J[3 * t + 2];
+  // J . grad l_k
+  double jg[4];
+  jg[1] = (Jx * c23[0] + Jy * c23[1] + Jz * c23[2]) * id;
+  jg[2] = (Jx * c31[0] + Jy * c31[1] + Jz * c31[2]) * id;
+  jg[3] = (Jx * c12[0] + Jy * c12[1] + Jz * c12[2]) * id;
+  jg[0] = -(jg[1] + jg[2] + jg[3]);
+  constexpr int ea[6] = {0, 0, 0, 1, 1, 2};
+  constexpr int eb[6] = {1, 2, 3, 2, 3, 3};
+  const uint8_t sb = signbits[t];
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    const double sgn = ((sb >> l) & 1) ? -1.0 : 1.0;
+    rbuf[(int64_t)l * nt + t] = sgn * v4 * (jg[eb[l]] - jg[ea[l]]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve kernels
+// ---------------------------------------------------------------------------
+constexpr int kLanes = 8;   // lanes per CSR row
+
+// t_n = (tau / D0_n) sum_e W~_en x_e   (W~^T rows = nodes)
+__global__ __launch_bounds__(kThreads) void k_wt(int64_t nv, const int* __restrict__ wtrowptr,
+                                                 const int* __restrict__ wtcol, const double* __restrict__ wtval,
+                                                 const double* __restrict__ d0tau, const double2* __restrict__ x,
+                                                 double2* __restrict__ t) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+  const int lane = threadIdx.x % kLanes;
+  double2 acc = make_double2(0.0, 0.0);
+  if (row < nv)
+    for (int p = wtrowptr[row] + lane; p < wtrowptr[row + 1]; p += kLanes) acc = rfma(wtval[p], x[wtcol[p]], acc);
+  for (int o = kLanes / 2; o > 0; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o, kLanes);
+    acc.y += __shfl_xor(acc.y, o, kLanes);
+  }
+  if (row < nv && lane == 0) {
+    const double f = d0tau[row];
+    t[row] = make_double2(acc.x * f, acc.y * f);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_spmv(int64_t n, int64_t ne, const int* __restrict__ rowptr,
+                                                   const int* __restrict__ col, const double2* __restrict__ val,
+                                                   const int* __restrict__ wrowptr, const int* __restrict__ wcol,
+                                                   const double* __restrict__ wval, const double2* __restrict__ t,
+                                                   const double2* __restrict__ x, const double2* __restrict__ b,
+                                                   double2* __restrict__ y) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+  const int lane = threadIdx.x % kLanes;
+  double2 acc = make_double2(0.0, 0.0);
+  if (row < n) {
+    for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) acc = cfma(val[p], x[col[p]], acc);
+    if (row < ne)
+      for (int p = wrowptr[row] + lane; p < wrowptr[row + 1]; p += kLanes) acc = rfma(wval[p], t[wcol[p]], acc);
+  }
+  for (int o = kLanes / 2; o > 0; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o, kLanes);
+    acc.y += __shfl_xor(acc.y, o, kLanes);
+  }
+  if (row < n && lane == 0) y[row] = b ? csub(b[row], acc) : acc;
+}
+
+// z_I = Minv_I r_I, one 64-lane wavefront per block, 4 blocks per workgroup.
+__global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int* __restrict__ blk_ptr,
+                                                          const int* __restrict__ blk_dofs,
+                                                          const double2* __restrict__ minv,
+                                                          const double2* __restrict__ r, double2* __restrict__ z) {
+  __shared__ double2 rl[4][kMaxBlock];
+  const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + w;
+  int b0 = 0, sz = 0, dof = -1;
+  if (k < nb) {
+    b0 = blk_ptr[k];
+    sz = blk_ptr[k + 1] - b0;
+    if (i < sz) dof = blk_dofs[b0 + i];
+  }
+  rl[w][i] = dof >= 0 ? r[dof] : make_double2(0.0, 0.0);
+  __syncthreads();
+  if (dof < 0) return;
+  const double2* Mk = minv + k * kMaxBlock * kMaxBlock;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int j = 0; j < sz; ++j) acc = cfma(Mk[j * kMaxBlock + i], rl[w][j], acc);
+  z[dof] = acc;
+}
+
+// partial[(c*8+k) * kRedBlocks + blockIdx.x] = sum_i conj(V_{c*8+k}[i]) w[i]
+__global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const double2* __restrict__ V, int64_t ldv, int q,
+                                                   const double2* __restrict__ w, double2* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int c0 = blockIdx.y * 8;
+  const int cnt = min(8, q - c0);
+  double2 acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 wi = w[i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < cnt) acc[k] = cfma_conj(V[(int64_t)(c0 + k) * ldv + i], wi, acc[k]);
+  }
+  for (int k = 0; k < cnt; ++k) {
+    const double re = block_sum(acc[k].x, sh);
+    const double im = block_sum(acc[k].y, sh);
+    if (threadIdx.x == 0) partial[(int64_t)(c0 + k) * kRedBlocks + blockIdx.x] = make_double2(re, im);
+  }
+}
+
+// out[k] = sum_b partial[k * kRedBlocks + b]  (fixed tree per column)
+__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restrict__ partial,
+                                                          double2* __restrict__ out) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) {
+    re += partial[(int64_t)k * kRedBlocks + b].x;
+    im += partial[(int64_t)k * kRedBlocks + b].y;
+  }
+  re = block_sum(re, sh);
+  im = block_sum(im, sh);
+  if (threadIdx.x == 0) out[k] = make_double2(re, im);
+}
+
+// w -= sum_k V_k h_k
+__global__ __launch_bounds__(kThreads) void k_update(int64_t n, const double2* __restrict__ V, int64_t ldv, int q,
+                                                     const double2* __restrict__ h, double2* __restrict__ w) {
+  __shared__ double2 hs[kMaxRestart + 1];
+  if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 acc = w[i];
+  for (int k = 0; k < q; ++k) {
+    const double2 v = V[(int64_t)k * ldv + i];
+    const double2 hk = hs[k];
+    acc.x -= v.x * hk.x - v.y * hk.y;
+    acc.y -= v.x * hk.y + v.y * hk.x;
+  }
+  w[i] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_norm2_partial(int64_t n, const double2* __restrict__ w,
+                                                            double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = w[i];
+    acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_norm2_final(const double* __restrict__ partial,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) acc += partial[b];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = sqrt(acc);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const double2* __restrict__ w,
+                                                           const double* __restrict__ nrm, double2* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = nrm[0];
+  const double f = a > 0.0 ? 1.0 / a : 0.0;
+  const double2 x = w[i];
+  v[i] = make_double2(x.x * f, x.y * f);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_host(int64_t n, const double2* __restrict__ w, double a,
+                                                         double2* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 x = w[i];
+  v[i] = make_double2(x.x * a, x.y * a);
+}
+
+__global__ __launch_bounds__(kThreads) void k_combine(int64_t n, const double2* __restrict__ V, int64_t ldv, int q,
+                                                      const double2* __restrict__ y, double2* __restrict__ u) {
+  __shared__ double2 ys[kMaxRestart + 1];
+  if (threadIdx.x < q) ys[threadIdx.x] = y[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < q; ++k) acc = cfma(V[(int64_t)k * ldv + i], ys[k], acc);
+  u[i] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const double2* __restrict__ z, double2* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = cadd(x[i], z[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_diag_scale(int64_t n, const double2* __restrict__ in,
+                                                         const double* __restrict__ s, int divide,
+                                                         double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double f = divide ? 1.0 / s[i] : s[i];
+  const double2 v = in[i];
+  out[i] = make_double2(v.x * f, v.y * f);
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero(int64_t n, double2* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = make_double2(0.0, 0.0);
+}
+
+// One workgroup per conductor component: mass-weighted mean of V over it.
+__global__ __launch_bounds__(kThreads) void k_vmean(int64_t nc, const int* __restrict__ comp,
+                                                    const double* __restrict__ lumped, const double2* __restrict__ V,
+                                                    double2* __restrict__ mean) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  double re = 0.0, im = 0.0, den = 0.0;
+  for (int64_t i = threadIdx.x; i < nc; i += blockDim.x)
+    if (comp[i] == c) {
+      const double m = lumped[i];
+      re = fma(m, V[i].x, re);
+      im = fma(m, V[i].y, im);
+      den += m;
+    }
+  re = block_sum(re, sh);
+  im = block_sum(im, sh);
+  den = block_sum(den, sh);
+  if (threadIdx.x == 0) mean[c] = make_double2(re / den, im / den);
+}
+
+__global__ __launch_bounds__(kThreads) void k_vmean_sub(int64_t nc, const int* __restrict__ comp,
+                                                        const double2* __restrict__ mean, double2* __restrict__ V) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) V[i] = csub(V[i], mean[comp[i]]);
+}
+
+// partial sums of a_i * b_i (unconjugated)
+__global__ __launch_bounds__(kThreads) void k_udot_partial(int64_t n, const double2* __restrict__ a,
+                                                           const double2* __restrict__ b,
+                                                           double2* __restrict__ partial) {
+  __shared__ double sh[4];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc = cfma(a[i], b[i], acc);
+  const double re = block_sum(acc.x, sh);
+  const double im = block_sum(acc.y, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(re, im);
+}
+
+__global__ __launch_bounds__(kThreads) void k_edge_field(int64_t ne, const int* __restrict__ edge_v,
+                                                         const double2* __restrict__ x, double omega,
+                                                         double2* __restrict__ E) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double2 a = x[e];
+  double2 v = make_double2(-omega * a.y, omega * a.x);
+  const int lo = edge_v[2 * e], hi = edge_v[2 * e + 1];
+  if (lo >= 0 && hi >= 0) v = cadd(v, csub(x[ne + hi], x[ne + lo]));
+  E[e] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+void launch_element(int64_t nt, int64_t nct, const double* xyz, const int* tet, const int* region,
+                    const uint8_t* signbits, const int* cidx, const double* nu_reg, const double* sig_reg,
+                    double omega, double delta_v, double2* ebuf, double* wbuf, double* vol4, hipStream_t st) {
+  k_element<<<blocks_for(nt), kThreads, 0, st>>>(nt, nct, xyz, tet, region, signbits, cidx, nu_reg, sig_reg, omega,
+                                                 delta_v, ebuf, wbuf, vol4);
+}
+void launch_gather_c(int64_t n, const int* ptr, const int* list, const double2* buf, double2* out, hipStream_t st) {
+  k_gather_c<<<blocks_for(n), kThreads, 0, st>>>(n, ptr, list, buf, out);
+}
+void launch_gather_r(int64_t n, const int* ptr, const int* list, const double* buf, double* out, hipStream_t st) {
+  k_gather_r<<<blocks_for(n), kThreads, 0, st>>>(n, ptr, list, buf, out);
+}
+void launch_gather_r2c(int64_t n, int64_t ntot, const int* ptr, const int* list, const double* buf, double2* out,
+                       hipStream_t st) {
+  k_gather_r2c<<<blocks_for(ntot), kThreads, 0, st>>>(n, ntot, ptr, list, buf, out);
+}
+void launch_permute_r(int64_t n, const int* perm, const double* in, double* out, hipStream_t st) {
+  k_permute_r<<<blocks_for(n), kThreads, 0, st>>>(n, perm, in, out);
+}
+void launch_d0tau(int64_t nv, const double* d0, double tau, double* d0tau, hipStream_t st) {
+  k_d0tau<<<blocks_for(nv), kThreads, 0, st>>>(nv, d0, tau, d0tau);
+}
+void launch_equilibrate(int64_t n, int64_t ne, const int* diagpos, const double2* val, const int* wrowptr,
+                        const int* wcol, const double* wval, const double* d0tau, double* s, int* status,
+                        hipStream_t st) {
+  k_equilibrate<<<blocks_for(n), kThreads, 0, st>>>(n, ne, diagpos, val, wrowptr, wcol, wval, d0tau, s, status);
+}
+void launch_scale_rows(int64_t n, const int* rowptr, const int* col, double2* val, const double* s, hipStream_t st) {
+  k_scale_rows<<<blocks_for(n), kThreads, 0, st>>>(n, rowptr, col, val, s);
+}
+void launch_scale_w(int64_t ne, const int* wrowptr, double* wval, const double* s, hipStream_t st) {
+  k_scale_w<<<blocks_for(ne), kThreads, 0, st>>>(ne, wrowptr, wval, s);
+}
+void launch_block_invert(int64_t nb, const int* blk_ptr, const int* blk_dofs, const int* blk_of, const int* loc_of,
+                         const int* rowptr, const int* col, const double2* val, int64_t ne, const int* wrowptr,
+                         const int* wcol, const double* wval, const int* wtrowptr, const int* wtcol,
+                         const double* wtval, const double* d0tau, double2* minv, int* status, hipStream_t st) {
+  if (nb <= 0) return;
+  k_block_invert<<<(unsigned)nb, kMaxBlock, 0, st>>>(blk_ptr, blk_dofs, blk_of, loc_of, rowptr, col, val, ne,
+                                                      wrowptr, wcol, wval, wtrowptr, wtcol, wtval, d0tau, minv,
+                                                      status);
+}
+void launch_rhs_elem(int64_t nt, const double* xyz, const int* tet, const uint8_t* signbits, const double* J,
+                     double* rbuf, hipStream_t st) {
+  k_rhs_elem<<<blocks_for(nt), kThreads, 0, st>>>(nt, xyz, tet, signbits, J, rbuf);
+}
+void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const double* d0tau,
+               const double2* x, double2* t, hipStream_t st) {
+  k_wt<<<blocks_for(nv * kLanes), kThreads, 0, st>>>(nv, wtrowptr, wtcol, wtval, d0tau, x, t);
+}
+void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const double2* val, const int* wrowptr,
+                 const int* wcol, const double* wval, const double2* t, const double2* x, const double2* b,
+                 double2* y, hipStream_t st) {
+  k_spmv<<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, ne, rowptr, col, val, wrowptr, wcol, wval, t, x, b, y);
+}
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const double2* minv, const double2* r,
+                        double2* z, hipStream_t st) {
+  k_block_apply<<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
+}
+void launch_mdot(int64_t n, const double2* V, int64_t ldv, int q, const double2* w, double2* partial, hipStream_t st) {
+  dim3 grid(kRedBlocks, (q + 7) / 8);
+  k_mdot<<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial);
+}
+void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st) {
+  k_reduce_cols<<<q, kThreads, 0, st>>>(partial, out);
+}
+void launch_update(int64_t n, const double2* V, int64_t ldv, int q, const double2* h, double2* w, hipStream_t st) {
+  k_update<<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, h, w);
+}
+void launch_norm2(int64_t n, const double2* w, double* partial, double* out_norm, hipStream_t st) {
+  k_norm2_partial<<<kRedBlocks, kThreads, 0, st>>>(n, w, partial);
+  k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm);
+}
+void launch_scale_by_inv(int64_t n, const double2* w, const double* norm, double2* v, hipStream_t st) {
+  k_scale_by_inv<<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v);
+}
+void launch_scale_host(int64_t n, const double2* w, double a, double2* v, hipStream_t st) {
+  k_scale_host<<<blocks_for(n), kThreads, 0, st>>>(n, w, a, v);
+}
+void launch_combine(int64_t n, const double2* V, int64_t ldv, int q, const double2* y, double2* u, hipStream_t st) {
+  k_combine<<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, y, u);
+}
+void launch_axpy(int64_t n, const double2* z, double2* x, hipStream_t st) {
+  k_axpy<<<blocks_for(n), kThreads, 0, st>>>(n, z, x);
+}
+void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st) {
+  k_diag_scale<<<blocks_for(n), kThreads, 0, st>>>(n, in, s, divide, out);
+}
+void launch_zero(int64_t n, double2* x, hipStream_t st) { k_zero<<<blocks_for(n), kThreads, 0, st>>>(n, x); }
+void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, double2* V, double2* scratch,
+                  hipStream_t st) {
+  if (ncomp <= 0 || nc <= 0) return;
+  k_vmean<<<ncomp, kThreads, 0, st>>>(nc, comp, lumped, V, scratch);
+  k_vmean_sub<<<blocks_for(nc), kThreads, 0, st>>>(nc, comp, scratch, V);
+}
+void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st) {
+  k_udot_partial<<<kRedBlocks, kThreads, 0, st>>>(n, a, b, partial);
+  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, out);
+}
+void launch_edge_field(int64_t ne, const int* edge_v, const double2* x, double omega, double2* E, hipStream_t st) {
+  k_edge_field<<<blocks_for(ne), kThreads, 0, st>>>(ne, edge_v, x, omega, E);
+}
+
+}  // namespace eddy

@@ -1,0 +1,379 @@
+// Host-side mesh processing: edges, conductor maps, the structural CSR
+// pattern of the A-V matrix, the W pattern, and the scatter lists that let
+// the GPU assemble every matrix entry as a fixed-order sum of element values
+// (no atomics).  Also the block-Jacobi partition (recursive coordinate
+// bisection).  Pure integer/geometry work; all numerics run on the GPU.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <numeric>
+#include <thread>
+
+#include "internal.h"
+
+namespace eddy {
+namespace {
+
+template <class F>
+void parallel_chunks(int64_t n, F&& fn) {
+  unsigned hc = std::thread::hardware_concurrency();
+  int nth = (int)std::min<unsigned>(hc ? hc : 4, 16);
+  if (n < 4096) nth = 1;
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nth - 1) / nth;
+  for (int i = 0; i < nth; ++i) {
+    int64_t b = i * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    th.emplace_back([&fn, i, b, e] { fn(i, b, e); });
+  }
+  for (auto& t : th) t.join();
+}
+
+// Stable counting sort of `keys` (0..nkeys-1): returns ptr[nkeys+1] and the
+// positions of the items grouped by key, in increasing item order per key.
+void group_by(const std::vector<int32_t>& keys, int64_t nkeys, std::vector<int32_t>& ptr,
+              std::vector<int32_t>& items) {
+  ptr.assign(nkeys + 1, 0);
+  for (int32_t k : keys) ptr[k + 1]++;
+  for (int64_t i = 0; i < nkeys; ++i) ptr[i + 1] += ptr[i];
+  items.resize(keys.size());
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (size_t i = 0; i < keys.size(); ++i) items[fill[keys[i]]++] = (int32_t)i;
+}
+
+// Build one CSR structure from per-row (col, contribution) lists produced by
+// `gen(row, out)`; entries keep insertion order within equal columns.
+template <class Gen>
+void build_rows(int64_t nrows, Gen&& gen, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
+                std::vector<int32_t>& cptr, std::vector<int32_t>& clist) {
+  struct Part {
+    std::vector<int32_t> rowlen, col, clen, clist;
+  };
+  unsigned hc = std::thread::hardware_concurrency();
+  int nth = (int)std::min<unsigned>(hc ? hc : 4, 16);
+  std::vector<Part> parts(nth);
+  int64_t chunk = (nrows + nth - 1) / nth;
+  std::vector<std::thread> th;
+  for (int i = 0; i < nth; ++i) {
+    int64_t b = i * chunk, e = std::min(nrows, b + chunk);
+    th.emplace_back([&, i, b, e] {
+      Part& P = parts[i];
+      std::vector<std::pair<int32_t, int32_t>> buf;
+      std::vector<int32_t> ord;
+      for (int64_t r = b; r < e; ++r) {
+        buf.clear();
+        gen(r, buf);
+        ord.resize(buf.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return buf[a].first < buf[c].first; });
+        int32_t len = 0;
+        for (size_t k = 0; k < ord.size(); ++k) {
+          const auto& pr = buf[ord[k]];
+          if (k == 0 || pr.first != buf[ord[k - 1]].first) {
+            P.col.push_back(pr.first);
+            P.clen.push_back(0);
+            ++len;
+          }
+          P.clen.back()++;
+          P.clist.push_back(pr.second);
+        }
+        P.rowlen.push_back(len);
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  rowptr.assign(nrows + 1, 0);
+  int64_t r = 0, nnz = 0, nc = 0;
+  for (auto& P : parts) {
+    for (int32_t l : P.rowlen) {
+      rowptr[r + 1] = rowptr[r] + l;
+      ++r;
+    }
+    nnz += P.col.size();
+    nc += P.clist.size();
+  }
+  col.resize(nnz);
+  cptr.assign(nnz + 1, 0);
+  clist.resize(nc);
+  int64_t oc = 0, ol = 0, oe = 0;
+  for (auto& P : parts) {
+    std::copy(P.col.begin(), P.col.end(), col.begin() + oc);
+    for (size_t k = 0; k < P.clen.size(); ++k) cptr[oe + k + 1] = P.clen[k];
+    std::copy(P.clist.begin(), P.clist.end(), clist.begin() + ol);
+    oc += P.col.size();
+    oe += P.clen.size();
+    ol += P.clist.size();
+  }
+  for (int64_t k = 0; k < nnz; ++k) cptr[k + 1] += cptr[k];
+}
+
+int find_root(std::vector<int32_t>& p, int32_t x) {
+  while (p[x] != x) {
+    p[x] = p[p[x]];
+    x = p[x];
+  }
+  return x;
+}
+
+}  // namespace
+
+eddy_status build_mesh(eddy_mesh* m) {
+  const int64_t nv = m->nv, nt = m->nt;
+  const int32_t* T = m->tet.data();
+  // ---- validation
+  for (int64_t i = 0; i < nt * 4; ++i)
+    if (T[i] < 0 || T[i] >= nv) { set_error("tet node index out of range"); return EDDY_ERR_ARG; }
+  for (int64_t t = 0; t < nt; ++t)
+    if (m->region[t] < 0 || m->region[t] >= m->nreg) { set_error("region id out of range"); return EDDY_ERR_ARG; }
+  {
+    std::atomic<int64_t> bad{-1};
+    parallel_chunks(nt, [&](int, int64_t b, int64_t e) {
+      for (int64_t t = b; t < e; ++t) {
+        const double* p[4];
+        for (int k = 0; k < 4; ++k) p[k] = &m->xyz[3 * (int64_t)T[4 * t + k]];
+        double E[3][3], L = 0;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) E[i][j] = p[i + 1][j] - p[0][j];
+        for (auto& le : kLocalEdge) {
+          double d2 = 0;
+          for (int j = 0; j < 3; ++j) d2 += (p[le[1]][j] - p[le[0]][j]) * (p[le[1]][j] - p[le[0]][j]);
+          L = std::max(L, d2);
+        }
+        double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                     E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                     E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+        if (!(std::fabs(det) > 1e-12 * L * std::sqrt(L))) bad = t;
+      }
+    });
+    if (bad.load() >= 0) { set_error("degenerate tetrahedron " + std::to_string(bad.load())); return EDDY_ERR_MESH; }
+  }
+  // ---- edges: group local edges by their low node, sort each group by the high node
+  std::vector<int32_t> lo(nt * 6), hi(nt * 6);
+  m->signbits.assign(nt, 0);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int l = 0; l < 6; ++l) {
+      int32_t a = T[4 * t + kLocalEdge[l][0]], b = T[4 * t + kLocalEdge[l][1]];
+      lo[6 * t + l] = std::min(a, b);
+      hi[6 * t + l] = std::max(a, b);
+      if (a > b) m->signbits[t] |= (uint8_t)(1u << l);
+    }
+  std::vector<int32_t> bptr, occ;
+  group_by(lo, nv, bptr, occ);
+  m->tet2edge.assign(nt * 6, -1);
+  m->edges.clear();
+  {
+    std::vector<int32_t> tmp;
+    int32_t eid = 0;
+    for (int64_t a = 0; a < nv; ++a) {
+      tmp.assign(occ.begin() + bptr[a], occ.begin() + bptr[a + 1]);
+      std::stable_sort(tmp.begin(), tmp.end(), [&](int32_t x, int32_t y) { return hi[x] < hi[y]; });
+      for (size_t k = 0; k < tmp.size(); ++k) {
+        if (k == 0 || hi[tmp[k]] != hi[tmp[k - 1]]) {
+          m->edges.push_back((int32_t)a);
+          m->edges.push_back(hi[tmp[k]]);
+          ++eid;
+        }
+        m->tet2edge[tmp[k]] = eid - 1;
+      }
+    }
+    m->ne = eid;
+  }
+  const int64_t ne = m->ne;
+  // ---- conductor maps
+  m->cidx.assign(nt, -1);
+  m->vmap.assign(nv, -1);
+  int64_t nct = 0;
+  for (int64_t t = 0; t < nt; ++t)
+    if (m->is_cond[m->region[t]]) {
+      m->cidx[t] = (int32_t)nct++;
+      for (int k = 0; k < 4; ++k) m->vmap[T[4 * t + k]] = 0;
+    }
+  m->nct = nct;
+  m->cond_nodes.clear();
+  for (int64_t n = 0; n < nv; ++n)
+    if (m->vmap[n] == 0) {
+      m->vmap[n] = (int32_t)m->cond_nodes.size();
+      m->cond_nodes.push_back((int32_t)n);
+    }
+  m->nc = (int64_t)m->cond_nodes.size();
+  const int64_t nc = m->nc;
+  // conductor components (union-find over conducting tetrahedra)
+  {
+    std::vector<int32_t> par(nc);
+    std::iota(par.begin(), par.end(), 0);
+    for (int64_t t = 0; t < nt; ++t)
+      if (m->cidx[t] >= 0) {
+        int32_t r0 = find_root(par, m->vmap[T[4 * t]]);
+        for (int k = 1; k < 4; ++k) {
+          int32_t rk = find_root(par, m->vmap[T[4 * t + k]]);
+          if (rk != r0) par[std::max(rk, r0)] = std::min(rk, r0), r0 = std::min(rk, r0);
+        }
+      }
+    m->comp.assign(nc, -1);
+    std::vector<int32_t> label(nc, -1);
+    int32_t nl = 0;
+    for (int64_t i = 0; i < nc; ++i) {
+      int32_t r = find_root(par, (int32_t)i);
+      if (label[r] < 0) label[r] = nl++;
+      m->comp[i] = label[r];
+    }
+    m->ncomp = nl;
+  }
+  m->edge_v.assign(ne * 2, -1);
+  for (int64_t t = 0; t < nt; ++t)
+    if (m->cidx[t] >= 0)
+      for (int l = 0; l < 6; ++l) {
+        int32_t e = m->tet2edge[6 * t + l];
+        m->edge_v[2 * e] = m->vmap[m->edges[2 * e]];
+        m->edge_v[2 * e + 1] = m->vmap[m->edges[2 * e + 1]];
+      }
+  // ---- incidences: edge -> (t, l) occurrences; conductor node -> (t, k) in conducting tets
+  std::vector<int32_t> eptr, eocc;
+  group_by(m->tet2edge, ne, eptr, eocc);
+  std::vector<int32_t> vkeys;
+  std::vector<int32_t> vsrc;
+  vkeys.reserve(nct * 4);
+  vsrc.reserve(nct * 4);
+  for (int64_t t = 0; t < nt; ++t)
+    if (m->cidx[t] >= 0)
+      for (int k = 0; k < 4; ++k) {
+        vkeys.push_back(m->vmap[T[4 * t + k]]);
+        vsrc.push_back((int32_t)(4 * t + k));
+      }
+  std::vector<int32_t> vptr, vitem;
+  group_by(vkeys, nc, vptr, vitem);
+  for (auto& x : vitem) x = vsrc[x];   // -> 4*t + k, increasing t per node
+  // ---- M pattern + scatter lists
+  const int64_t AV0 = 21 * nt, VV0 = 21 * nt + 24 * nct;
+  auto genM = [&](int64_t r, std::vector<std::pair<int32_t, int32_t>>& out) {
+    if (r < ne) {
+      for (int32_t p = eptr[r]; p < eptr[r + 1]; ++p) {
+        int64_t o = eocc[p], t = o / 6;
+        int l = (int)(o % 6);
+        for (int mm = 0; mm < 6; ++mm)
+          out.emplace_back(m->tet2edge[6 * t + mm], (int32_t)(pair6(l, mm) * nt + t));
+        int32_t c = m->cidx[t];
+        if (c >= 0)
+          for (int k = 0; k < 4; ++k)
+            out.emplace_back((int32_t)(ne + m->vmap[T[4 * t + k]]), (int32_t)(AV0 + (l * 4 + k) * nct + c));
+      }
+    } else {
+      int64_t n = r - ne;
+      for (int32_t p = vptr[n]; p < vptr[n + 1]; ++p) {
+        int64_t o = vitem[p], t = o / 4;
+        int k = (int)(o % 4);
+        int32_t c = m->cidx[t];
+        for (int mm = 0; mm < 6; ++mm)
+          out.emplace_back(m->tet2edge[6 * t + mm], (int32_t)(AV0 + (mm * 4 + k) * nct + c));
+        for (int kk = 0; kk < 4; ++kk)
+          out.emplace_back((int32_t)(ne + m->vmap[T[4 * t + kk]]), (int32_t)(VV0 + pair4(k, kk) * nct + c));
+      }
+    }
+  };
+  if (21 * nt + 34 * nct >= (int64_t)INT32_MAX || 24 * nt >= (int64_t)INT32_MAX) {
+    set_error("mesh too large for 32-bit scatter indices");
+    return EDDY_ERR_ARG;
+  }
+  build_rows(ne + nc, genM, m->rowptr, m->col, m->cptr, m->clist);
+  if ((int64_t)m->clist.size() >= (int64_t)INT32_MAX) { set_error("too many contributions"); return EDDY_ERR_ARG; }
+  m->diagpos.assign(ne + nc, -1);
+  for (int64_t r = 0; r < ne + nc; ++r)
+    for (int32_t p = m->rowptr[r]; p < m->rowptr[r + 1]; ++p)
+      if (m->col[p] == r) m->diagpos[r] = p;
+  for (int64_t r = 0; r < ne + nc; ++r)
+    if (m->diagpos[r] < 0) { set_error("row without a diagonal entry"); return EDDY_ERR_MESH; }
+  // ---- W pattern + scatter lists
+  auto genW = [&](int64_t r, std::vector<std::pair<int32_t, int32_t>>& out) {
+    for (int32_t p = eptr[r]; p < eptr[r + 1]; ++p) {
+      int64_t o = eocc[p], t = o / 6;
+      int l = (int)(o % 6);
+      for (int k = 0; k < 4; ++k) out.emplace_back(T[4 * t + k], (int32_t)((l * 4 + k) * nt + t));
+    }
+  };
+  build_rows(ne, genW, m->wrowptr, m->wcol, m->wcptr, m->wclist);
+  group_by(m->wcol, nv, m->wtrowptr, m->wtperm);
+  m->wtcol.resize(m->wcol.size());
+  {
+    std::vector<int32_t> rowof(m->wcol.size());
+    for (int64_t r = 0; r < ne; ++r)
+      for (int32_t p = m->wrowptr[r]; p < m->wrowptr[r + 1]; ++p) rowof[p] = (int32_t)r;
+    for (size_t q = 0; q < m->wtperm.size(); ++q) m->wtcol[q] = rowof[m->wtperm[q]];
+  }
+  // ---- D0 (all tets), lumped conductor mass (conducting tets), rhs gathers
+  {
+    std::vector<int32_t> item;
+    group_by(m->tet, nv, m->d0ptr, item);
+    m->d0list.resize(item.size());
+    for (size_t i = 0; i < item.size(); ++i) m->d0list[i] = item[i] / 4;
+    m->lcptr = vptr;
+    m->lclist.resize(vitem.size());
+    for (size_t i = 0; i < vitem.size(); ++i) m->lclist[i] = vitem[i] / 4;
+    m->rptr = eptr;
+    m->rlist.resize(eocc.size());
+    for (size_t i = 0; i < eocc.size(); ++i) {
+      int64_t o = eocc[i];
+      m->rlist[i] = (int32_t)((o % 6) * nt + o / 6);
+    }
+  }
+  return EDDY_OK;
+}
+
+// Recursive coordinate bisection of the DOF positions (edge midpoints, then
+// conductor nodes).  A set S (sorted by DOF id) with nb = ceil(|S|/b) <= 1 is
+// a block; otherwise it is split along the axis of largest extent (lowest
+// axis on ties) after sorting by (coordinate, id), the left part receiving
+// floor(|S| * floor(nb/2) / nb) DOFs.  Blocks are emitted depth-first, left
+// first; DOFs inside a block are in increasing id.
+eddy_status build_blocks(eddy_mesh* m, int32_t b) {
+  if (m->blk_b == b) return EDDY_OK;
+  const int64_t n = m->ndof(), ne = m->ne;
+  std::vector<double> X(n * 3);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int j = 0; j < 3; ++j)
+      X[3 * e + j] = (m->xyz[3 * (int64_t)m->edges[2 * e] + j] + m->xyz[3 * (int64_t)m->edges[2 * e + 1] + j]) * 0.5;
+  for (int64_t c = 0; c < m->nc; ++c)
+    for (int j = 0; j < 3; ++j) X[3 * (ne + c) + j] = m->xyz[3 * (int64_t)m->cond_nodes[c] + j];
+  std::vector<int32_t> ids(n);
+  std::iota(ids.begin(), ids.end(), 0);
+  m->blk_ptr.assign(1, 0);
+  m->blk_dofs.clear();
+  m->blk_dofs.reserve(n);
+  struct Range { int64_t b, e; };
+  std::vector<Range> stack{{0, n}};
+  while (!stack.empty()) {
+    Range R = stack.back();
+    stack.pop_back();
+    int64_t sz = R.e - R.b;
+    int64_t nb = (sz + b - 1) / b;
+    if (nb <= 1) {
+      m->blk_dofs.insert(m->blk_dofs.end(), ids.begin() + R.b, ids.begin() + R.e);
+      m->blk_ptr.push_back((int32_t)m->blk_dofs.size());
+      continue;
+    }
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = R.b; i < R.e; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double v = X[3 * (int64_t)ids[i] + j];
+        mn[j] = std::min(mn[j], v);
+        mx[j] = std::max(mx[j], v);
+      }
+    int ax = 0;
+    double best = mx[0] - mn[0];
+    for (int j = 1; j < 3; ++j)
+      if (mx[j] - mn[j] > best) best = mx[j] - mn[j], ax = j;
+    auto first = ids.begin() + R.b, last = ids.begin() + R.e;
+    std::sort(first, last, [&](int32_t a, int32_t c) {
+      double xa = X[3 * (int64_t)a + ax], xc = X[3 * (int64_t)c + ax];
+      return xa < xc || (xa == xc && a < c);
+    });
+    int64_t s = (sz * (nb / 2)) / nb;
+    std::sort(first, first + s);
+    std::sort(first + s, last);
+    stack.push_back({R.b + s, R.e});
+    stack.push_back({R.b, R.b + s});
+  }
+  m->blk_b = b;
+  return EDDY_OK;
+}
+
+}  // namespace eddy

@@ -1,0 +1,287 @@
+"""Python binding of libeddy.so (argument marshalling only).
+
+Every step of the solver runs in the HIP library; this module only turns
+numpy arrays and torch device tensors into the plain pointers of the C ABI
+(include/eddy.h), allocates the device workspaces as torch tensors and passes
+torch's current HIP stream.  If the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeddy.so")
+
+
+class EddyError(RuntimeError):
+    pass
+
+
+class _Params(C.Structure):
+    _fields_ = [("tau_gauge", C.c_double), ("delta_v", C.c_double), ("block_size", C.c_int32)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("breakdown", C.c_int32), ("relres", C.c_double), ("est_relres", C.c_double),
+                ("seconds", C.c_double)]
+
+
+EXPORTS = [
+    "eddy_mesh_create", "eddy_mesh_destroy", "eddy_mesh_counts", "eddy_mesh_edges",
+    "eddy_mesh_conductor_nodes", "eddy_mesh_blocks", "eddy_op_workspace_bytes", "eddy_op_create",
+    "eddy_op_destroy", "eddy_op_assemble", "eddy_rhs_from_current", "eddy_solve_workspace_bytes",
+    "eddy_solve", "eddy_impedance", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile",
+    "eddy_status_string", "eddy_last_error",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1602_03207_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D, VP = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    sig = {
+        "eddy_mesh_create": [I64, P(D), I64, P(I32), P(I32), I32, P(I32), P(VP)],
+        "eddy_mesh_destroy": [VP],
+        "eddy_mesh_counts": [VP, P(I64), P(I64), P(I64), P(I64), P(I32)],
+        "eddy_mesh_edges": [VP, P(I32)],
+        "eddy_mesh_conductor_nodes": [VP, P(I32)],
+        "eddy_mesh_blocks": [VP, I32, P(I64), P(I32), P(I32)],
+        "eddy_op_workspace_bytes": [VP, P(_Params), P(C.c_size_t)],
+        "eddy_op_create": [VP, P(_Params), VP, C.c_size_t, VP, P(VP)],
+        "eddy_op_destroy": [VP],
+        "eddy_op_assemble": [VP, P(D), P(D), D, VP],
+        "eddy_rhs_from_current": [VP, VP, VP, VP],
+        "eddy_solve_workspace_bytes": [VP, P(_Opts), P(C.c_size_t)],
+        "eddy_solve": [VP, VP, VP, P(_Opts), VP, C.c_size_t, P(_Report), VP],
+        "eddy_impedance": [VP, I32, VP, I32, VP, P(D), P(D), VP],
+        "eddy_edge_field": [VP, VP, VP, VP],
+        "eddy_spmv": [VP, VP, VP, VP],
+        "eddy_precond_apply": [VP, VP, VP, VP],
+        "eddy_export": [VP, P(I32), P(I32), P(D), P(I32), P(I32), P(D), P(D), P(D), VP],
+        "eddy_profile": [VP, I32, P(D), P(I64)],
+        "eddy_status_string": [I32],
+        "eddy_last_error": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+    lib.eddy_mesh_destroy.restype = None
+    lib.eddy_op_destroy.restype = None
+    lib.eddy_status_string.restype = C.c_char_p
+    lib.eddy_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        msg = _lib.eddy_last_error().decode()
+        raise EddyError(f"{what}: {_lib.eddy_status_string(status).decode()} ({msg})")
+    return status
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """Host mesh handle: tetrahedra, regions, conductor flags per region."""
+
+    def __init__(self, xyz, tet, region, is_conductor):
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tet = np.ascontiguousarray(tet, dtype=np.int32)
+        self.region = np.ascontiguousarray(region, dtype=np.int32)
+        self.is_conductor = np.ascontiguousarray(np.asarray(is_conductor).astype(np.int32))
+        h = C.c_void_p()
+        _check(_lib.eddy_mesh_create(self.xyz.shape[0], _ptr(self.xyz, C.c_double), self.tet.shape[0],
+                                     _ptr(self.tet, C.c_int32), _ptr(self.region, C.c_int32),
+                                     self.is_conductor.size, _ptr(self.is_conductor, C.c_int32), C.byref(h)),
+               "eddy_mesh_create")
+        self._h = h
+        ne, nc, nnz, nnzw, ncomp = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(_lib.eddy_mesh_counts(h, C.byref(ne), C.byref(nc), C.byref(nnz), C.byref(nnzw), C.byref(ncomp)),
+               "eddy_mesh_counts")
+        self.nv, self.nt = self.xyz.shape[0], self.tet.shape[0]
+        self.ne, self.nc, self.nnz, self.nnz_w, self.ncomp = ne.value, nc.value, nnz.value, nnzw.value, ncomp.value
+        self.ndof = self.ne + self.nc
+
+    @classmethod
+    def from_synth(cls, mesh, conductor_regions):
+        flags = np.zeros(int(mesh.region.max()) + 1 if len(mesh.region_names) == 0 else len(mesh.region_names), np.int32)
+        flags[list(conductor_regions)] = 1
+        return cls(mesh.xyz, mesh.tet, mesh.region, flags)
+
+    def edges(self) -> np.ndarray:
+        out = np.empty((self.ne, 2), np.int32)
+        _check(_lib.eddy_mesh_edges(self._h, _ptr(out, C.c_int32)), "eddy_mesh_edges")
+        return out
+
+    def conductor_nodes(self) -> np.ndarray:
+        out = np.empty(self.nc, np.int32)
+        if self.nc:
+            _check(_lib.eddy_mesh_conductor_nodes(self._h, _ptr(out, C.c_int32)), "eddy_mesh_conductor_nodes")
+        return out
+
+    def blocks(self, block_size: int):
+        nb = C.c_int64()
+        _check(_lib.eddy_mesh_blocks(self._h, block_size, C.byref(nb), None, None), "eddy_mesh_blocks")
+        ptr = np.empty(nb.value + 1, np.int32)
+        dofs = np.empty(self.ndof, np.int32)
+        _check(_lib.eddy_mesh_blocks(self._h, block_size, C.byref(nb), _ptr(ptr, C.c_int32), _ptr(dofs, C.c_int32)),
+               "eddy_mesh_blocks")
+        return ptr, dofs
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.eddy_mesh_destroy(h)
+            self._h = None
+
+
+@dataclass
+class SolveReport:
+    iters: int
+    restarts: int
+    converged: bool
+    breakdown: bool
+    relres: float
+    est_relres: float
+    seconds: float
+
+
+def _aligned(nbytes: int, device):
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, C.c_void_p(buf.data_ptr() + off)
+
+
+class Operator:
+    """Device operator: workspace, assembly, RHS, solve and outputs."""
+
+    def __init__(self, mesh: Mesh, tau: float = 1.0, delta_v: float = 0.0, block_size: int = 64, device="cuda"):
+        import torch
+        self.mesh = mesh
+        self.device = torch.device(device)
+        self.params = _Params(tau, delta_v, block_size)
+        nbytes = C.c_size_t()
+        _check(_lib.eddy_op_workspace_bytes(mesh._h, C.byref(self.params), C.byref(nbytes)), "eddy_op_workspace_bytes")
+        self.ws_bytes = nbytes.value
+        self._ws, self._wsp = _aligned(self.ws_bytes, self.device)
+        h = C.c_void_p()
+        _check(_lib.eddy_op_create(mesh._h, C.byref(self.params), self._wsp, self.ws_bytes, _stream(), C.byref(h)),
+               "eddy_op_create")
+        self._h = h
+        self.ndof, self.ne, self.nc, self.nt, self.nv = mesh.ndof, mesh.ne, mesh.nc, mesh.nt, mesh.nv
+        self._solve_ws = None
+        self.omega = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.eddy_op_destroy(h)
+            self._h = None
+
+    def assemble(self, nu, sigma, omega: float):
+        nu = np.ascontiguousarray(nu, dtype=np.float64)
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        _check(_lib.eddy_op_assemble(self._h, _ptr(nu, C.c_double), _ptr(sigma, C.c_double), float(omega), _stream()),
+               "eddy_op_assemble")
+        self.omega = float(omega)
+
+    def _c128(self, n=None):
+        import torch
+        return torch.empty(self.ndof if n is None else n, dtype=torch.complex128, device=self.device)
+
+    def rhs_from_current(self, J, out=None):
+        """J: float64 device tensor [nt, 3] -> b: complex128 [ndof]."""
+        assert J.dtype.is_floating_point and J.is_contiguous() and J.numel() == 3 * self.nt
+        b = self._c128() if out is None else out
+        _check(_lib.eddy_rhs_from_current(self._h, _dev(J), _dev(b), _stream()), "eddy_rhs_from_current")
+        return b
+
+    def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None):
+        import torch
+        opts = _Opts(tol, restart, max_iter)
+        nbytes = C.c_size_t()
+        _check(_lib.eddy_solve_workspace_bytes(self._h, C.byref(opts), C.byref(nbytes)), "eddy_solve_workspace_bytes")
+        if self._solve_ws is None or self._solve_ws[2] < nbytes.value:
+            buf, p = _aligned(nbytes.value, self.device)
+            self._solve_ws = (buf, p, nbytes.value)
+        x = self._c128() if out is None else out
+        rep = _Report()
+        st = _check(_lib.eddy_solve(self._h, _dev(b), _dev(x), C.byref(opts), self._solve_ws[1], self._solve_ws[2],
+                                    C.byref(rep), _stream()), "eddy_solve")
+        return x, SolveReport(rep.iters, rep.restarts, bool(rep.converged), bool(rep.breakdown), rep.relres,
+                              rep.est_relres, rep.seconds)
+
+    def spmv(self, x, out=None):
+        y = self._c128() if out is None else out
+        _check(_lib.eddy_spmv(self._h, _dev(x), _dev(y), _stream()), "eddy_spmv")
+        return y
+
+    def precond_apply(self, r, out=None):
+        z = self._c128() if out is None else out
+        _check(_lib.eddy_precond_apply(self._h, _dev(r), _dev(z), _stream()), "eddy_precond_apply")
+        return z
+
+    def edge_field(self, x, out=None):
+        E = self._c128(self.ne) if out is None else out
+        _check(_lib.eddy_edge_field(self._h, _dev(x), _dev(E), _stream()), "eddy_edge_field")
+        return E
+
+    def impedance(self, xs, bs, currents):
+        """xs: [nsol, ndof], bs: [nsrc, ndof] complex128 device; returns Z[nsol, nsrc] (numpy)."""
+        xs = xs.reshape(-1, self.ndof).contiguous()
+        bs = bs.reshape(-1, self.ndof).contiguous()
+        cur = np.ascontiguousarray(currents, dtype=np.float64)
+        Z = np.empty((xs.shape[0], bs.shape[0]), dtype=np.complex128)
+        _check(_lib.eddy_impedance(self._h, xs.shape[0], _dev(xs), bs.shape[0], _dev(bs), _ptr(cur, C.c_double),
+                                   Z.ctypes.data_as(C.POINTER(C.c_double)), _stream()), "eddy_impedance")
+        return Z
+
+    PROFILE_CLASSES = ("block_apply", "gauge_wt", "spmv", "cgs2")
+
+    def profile(self, enable: bool = True):
+        """Read-and-reset the per-class GMRES kernel timings; enable/disable timing."""
+        ms = np.zeros(4)
+        cnt = np.zeros(4, np.int64)
+        _check(_lib.eddy_profile(self._h, int(enable), _ptr(ms, C.c_double), _ptr(cnt, C.c_int64)), "eddy_profile")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PROFILE_CLASSES)}
+
+    def export(self):
+        """Host copies of the stored arrays (see eddy_export)."""
+        m = self.mesh
+        out = {
+            "rowptr": np.empty(self.ndof + 1, np.int32), "col": np.empty(m.nnz, np.int32),
+            "val": np.empty(m.nnz, np.complex128), "wrowptr": np.empty(self.ne + 1, np.int32),
+            "wcol": np.empty(m.nnz_w, np.int32), "wval": np.empty(m.nnz_w, np.float64),
+            "d0": np.empty(self.nv, np.float64), "s": np.empty(self.ndof, np.float64),
+        }
+        I, D = C.c_int32, C.c_double
+        _check(_lib.eddy_export(self._h, _ptr(out["rowptr"], I), _ptr(out["col"], I),
+                                out["val"].ctypes.data_as(C.POINTER(D)), _ptr(out["wrowptr"], I), _ptr(out["wcol"], I),
+                                _ptr(out["wval"], D), _ptr(out["d0"], D), _ptr(out["s"], D), _stream()), "eddy_export")
+        return out
