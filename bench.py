@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Time one probe-position solve of the steam-generator tube model on one GPU.
+
+Workload: the ~2M-tetrahedron tube (conducting tube 9.84/11.11 mm, 1e6 S/m;
+support plate 2e6 S/m with four lobed holes; 60 mm air cylinder, 200 mm
+long), f = 100 kHz, two coaxial coils at probe position z = 0, plain FP64
+GMRES(30) with 64-DOF block-Jacobi to weighted relative residual 1e-8.
+
+One step = assemble the operator on the device (element kernel, scatter,
+equilibration, block inverses), right-hand sides of both coils, the GMRES
+solve for the generator coil, V-mean removal and the impedances Z11, Z21.
+Mesh topology and the CSR/scatter maps are built once on the host before
+timing (they depend on the mesh only).  Inputs are resident in HBM when the
+timed region starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["tube", "cube"], default="tube")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--block", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def workload(name):
+    import numpy as np
+    from synth import tube, tube_materials, probe_currents, cube, cube_current
+    if name == "tube":
+        m = tube()
+        nu, sig, omega = tube_materials(1e5)
+        J1, J2 = probe_currents(m, 0.0)
+        cond = [1, 2, 3]
+        tau = float(nu[0])
+        desc = {"workload": "sg_tube_2M_tets", "freq_hz": 1e5, "probe_z_m": 0.0}
+    else:
+        m = cube(8)
+        nu, sig, omega = np.array([1.0, 1.0]), np.array([0.0, 1.0]), 50.0
+        J1, J2 = cube_current(m, 0), cube_current(m, 1)
+        cond = [1]
+        tau = 1.0
+        desc = {"workload": "unit_cube_n8_3072_tets"}
+    return m, nu, sig, omega, J1, J2, cond, tau, desc
+
+
+def spmv_bytes(M, op):
+    """Algorithmic bytes of one k_spmv launch (CSR part + W~ t part)."""
+    n, ne, nv = op.ndof, op.ne, op.nv
+    return (20 * M.nnz + 4 * (n + 1) + 16 * n + 16 * n
+            + 12 * M.nnz_w + 4 * (ne + 1) + 16 * nv)
+
+
+def wt_bytes(M, op):
+    return 12 * M.nnz_w + 4 * (op.nv + 1) + 16 * op.ne + 16 * op.nv + 8 * op.nv
+
+
+def block_apply_bytes(M, op, block):
+    import numpy as np
+    ptr, _ = M.blocks(block)
+    sz = np.diff(ptr).astype(np.int64)
+    return int(16 * (sz * sz).sum() + 4 * (len(ptr)) + 4 * op.ndof + 32 * op.ndof)
+
+
+def cpu_baseline(args, gpu_iters):
+    """The oracle, timed on a bounded sample of the same workload.
+
+    Sample: the tube cross-section over a shortened axis (same radial and
+    azimuthal mesh, same conductors and coils, z in [-2, 2] mm with the
+    scan-zone spacing), full oracle setup (assembly, equilibration, dense
+    block inverses) plus one GMRES(30) cycle.  Scaled to the full workload as
+    setup * (nt_full / nt_sample) + (per-iteration time) * (ndof_full /
+    ndof_sample) * (GPU iteration count).
+    """
+    import numpy as np
+    from synth import tube, tube_materials, probe_currents
+    from oracle.assemble import assemble
+    from oracle.solve import BlockJacobi, gmres, equilibration
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    m = tube(scan_half=2e-3, z_half=2e-3, plate_half=1.6e-3)
+    nu, sig, omega = tube_materials(1e5)
+    J1, _ = probe_currents(m, 0.0)
+    t0 = time.perf_counter()
+    s = assemble(m.xyz, m.tet, m.region, nu, sig, omega, tau=nu[0], conductor_regions=[1, 2, 3])
+    b = s.rhs(J1)
+    sc = equilibration(s)
+    P = BlockJacobi.build(s, m.xyz, args.block, scale=sc)
+    t1 = time.perf_counter()
+    k = args.restart
+    res = gmres(lambda v: sc * s.matvec(sc * v), sc * b, P.apply, m=k, tol=1e-30, max_iter=k)
+    t2 = time.perf_counter()
+    return m.nt, s.ndof, t1 - t0, (t2 - t1) / max(res.iters, 1), threads
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is described "
+              f"in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1602_03207_amd import eddy
+
+    m, nu, sig, omega, J1, J2, cond, tau, desc = workload(args.workload)
+    flags = np.zeros(len(nu), np.int32)
+    flags[cond] = 1
+    th0 = time.perf_counter()
+    M = eddy.Mesh(m.xyz, m.tet, m.region, flags)
+    op = eddy.Operator(M, tau=tau, block_size=args.block)
+    torch.cuda.synchronize()
+    host_setup = time.perf_counter() - th0
+    J1d = torch.from_numpy(np.ascontiguousarray(J1)).cuda()
+    J2d = torch.from_numpy(np.ascontiguousarray(J2)).cuda()
+    b = torch.empty((2, op.ndof), dtype=torch.complex128, device="cuda")
+    x = torch.empty(op.ndof, dtype=torch.complex128, device="cuda")
+
+    def step():
+        op.assemble(nu, sig, omega)
+        op.rhs_from_current(J1d, out=b[0])
+        op.rhs_from_current(J2d, out=b[1])
+        _, rep = op.solve(b[0], tol=args.tol, restart=args.restart, max_iter=args.max_iter, out=x)
+        Z = op.impedance(x[None], b, [1.0, 1.0])
+        return rep, Z
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    op.profile(True)
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        reps.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = op.profile(False)
+    rep, Z = reps[-1]
+    sec_per_solve = elapsed / args.steps
+
+    kb = {
+        "block_apply": block_apply_bytes(M, op, args.block),
+        "gauge_wt": wt_bytes(M, op),
+        "spmv": spmv_bytes(M, op),
+    }
+    kernels = {}
+    for name, (ms, cnt) in prof.items():
+        avg = ms / max(cnt, 1)
+        entry = {"avg_ms": round(avg, 5), "launches": cnt, "total_ms": round(ms, 2)}
+        if name in kb and cnt:
+            gbs = kb[name] / (avg * 1e-3) / 1e9
+            entry.update({"bytes_per_launch": kb[name], "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[name] = entry
+    single = {k: v for k, v in kernels.items() if k in kb and v["launches"]}
+    dom = max(single, key=lambda k: single[k]["total_ms"]) if single else "spmv"
+    roof = None
+    if dom in single:
+        d = single[dom]
+        roof = {"bound": "hbm", "kernel": {"block_apply": "k_block_apply", "gauge_wt": "k_wt", "spmv": "k_spmv"}[dom],
+                "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"], "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline and args.workload == "tube":
+        nt_s, nd_s, t_setup, t_it, threads = cpu_baseline(args, rep.iters)
+        est = t_setup * (M.nt / nt_s) + t_it * (op.ndof / nd_s) * rep.iters
+        cpu = {"value": round(est, 2), "unit": "s per probe-position solve", "cores": threads, "kind": "oracle",
+               "sample": (f"oracle on the tube cross-section over z in [-2,2] mm ({nt_s} tets, {nd_s} DOF): "
+                          f"setup {t_setup:.2f} s + {t_it:.3f} s per GMRES iteration, scaled linearly to "
+                          f"{M.nt} tets / {op.ndof} DOF and to the GPU's {rep.iters} iterations")}
+
+    out = {
+        "metric": "s per probe-position solve at rel-res 1e-8 (plain FP64 GMRES + block-Jacobi); SpMV GB/s",
+        "value": round(sec_per_solve, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec_per_solve * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128 (f64)",
+        "data": "synthetic",
+        "config": {**desc, "tets": M.nt, "dof": op.ndof, "nnz": M.nnz, "nnz_w": M.nnz_w, "block": args.block,
+                   "restart": args.restart, "tol": args.tol, "precision": "fp64", "parallelism": "single GPU"},
+        "solve": {"iters": rep.iters, "restarts": rep.restarts, "converged": rep.converged, "relres": rep.relres,
+                  "Z11": [Z[0, 0].real, Z[0, 0].imag], "Z21": [Z[0, 1].real, Z[0, 1].imag]},
+        "host_setup_s": round(host_setup, 2),
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

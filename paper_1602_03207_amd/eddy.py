@@ -155,7 +155,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.eddy_mesh_destroy(h)
             self._h = None
 
@@ -200,7 +200,7 @@ class Operator:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.eddy_op_destroy(h)
             self._h = None
 
