@@ -79,6 +79,10 @@ typedef struct {
   double relres;       /* true weighted relative residual of the returned x        */
   double est_relres;   /* Arnoldi estimate at exit                                 */
   double seconds;      /* wall time of the call                                    */
+  int32_t gauge_in_operator;  /* 1: iterated on the gauged operator; 0: on the    */
+                              /* penalty-free operator + Coulomb projection        */
+  int32_t cg_iters;    /* CG steps of the projection's nodal Poisson solve         */
+  double div_residual; /* ||G^T b_A|| / ||b||: discrete divergence of the source   */
 } eddy_solve_report;
 
 /* ---- mesh (host) -------------------------------------------------------
@@ -133,7 +137,15 @@ eddy_status eddy_rhs_from_current(const eddy_op* op, const double* J_dev, eddy_c
 /* ---- solve -------------------------------------------------------------
  * Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt
  * applied twice (CGS2), block-Jacobi preconditioning, on the equilibrated
- * system; x0 = 0.  b_dev[ndof] and x_dev[ndof] are device buffers (may not
+ * system; x0 = 0.  When delta_V = 0 and the source is divergence-free
+ * (||G^T b_A|| <= 1e-10 ||b||, as Section 2 requires of the excitation), the
+ * gauged solution has W^T A = 0, so GMRES iterates on the operator without
+ * the penalty term (its kernel {(G psi, -i omega psi|_c)} is harmless for
+ * such sources) with the gauged blocks as preconditioner, and the Coulomb
+ * gauge of Eq. 3 is then restored by the projection A -= G psi,
+ * V += i omega psi|_c, (W^T G) psi = W^T A (nodal Jacobi-CG).  Otherwise it
+ * iterates on the gauged operator.  Either way `relres` is the gauged
+ * system's true weighted residual at the returned x.  b_dev[ndof] and x_dev[ndof] are device buffers (may not
  * alias).  On return x holds [A ; V] with the mass-weighted mean of V removed
  * per conductor component (Section 4).  ws: device workspace of at least
  * eddy_solve_workspace_bytes.  rep (host) may be NULL. */

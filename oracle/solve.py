@@ -12,6 +12,17 @@
   Hessenberg least-squares problem, and block-Jacobi preconditioning.  The
   stopping test is on the true equilibrated residual, i.e. the residual in
   the D^-1/2-weighted norm.
+* ``solve_gmres``: the plain FP64 method.  The excitation must be
+  divergence-free (Section 2, below Eq. 1); then, with delta_V = 0, the
+  gauged system's solution has W^T A = 0, so the penalty term contributes
+  nothing at the solution.  The Krylov iteration therefore runs on the
+  operator without the penalty (singular, but consistent for such sources,
+  its kernel being {(G psi, -i omega psi|_c)}) while the block-Jacobi blocks
+  keep it (they must be invertible); the Coulomb gauge of Eq. 3 is then
+  restored exactly by the discrete projection A <- A - G psi,
+  V <- V + i omega psi|_c with (W^T G) psi = W^T A.  This returns the gauged
+  system's solution.  For sources that are not divergence-free, or
+  delta_V > 0, it iterates on the gauged operator instead.
 """
 from __future__ import annotations
 
@@ -194,10 +205,49 @@ def gmres(matvec, b: np.ndarray, precond, m: int = 30, tol: float = 1e-10, max_i
     return GmresResult(x, it, restarts, beta / bnorm, hist, beta / bnorm <= tol)
 
 
+def divergence_residual(sysm: System, b: np.ndarray) -> float:
+    """||G^T b_A|| / ||b||: zero (to rounding) for divergence-free currents."""
+    from .topology import gradient_matrix
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(gradient_matrix(sysm.topo).T @ b[: sysm.topo.ne]) / nb) if nb else 0.0
+
+
+def coulomb_projection(sysm: System, x: np.ndarray) -> np.ndarray:
+    """Shift x along the kernel {(G psi, -i omega psi|_c)} so that W^T A = 0."""
+    from .topology import gradient_matrix
+    topo = sysm.topo
+    G = gradient_matrix(topo)
+    L = (sysm.W.T @ G).tocsc()                  # = G^T M_1 G, the P1 stiffness (Laplacian)
+    rhs = sysm.W.T @ x[: topo.ne]
+    keep = np.arange(1, topo.nv)                # constants are in the kernel of L: pin node 0
+    psi = np.zeros(topo.nv, dtype=complex)
+    psi[keep] = spla.spsolve(L[keep][:, keep], rhs[keep])
+    y = x.copy()
+    y[: topo.ne] -= G @ psi
+    y[topo.ne:] += 1j * sysm.omega * psi[topo.cond_nodes]
+    return y
+
+
 def solve_gmres(sysm: System, xyz: np.ndarray, b: np.ndarray, block: int = 64, m: int = 30,
-                tol: float = 1e-10, max_iter: int = 5000):
-    """Plain FP64 method: equilibrate, block-Jacobi, GMRES(m); returns (x, result)."""
+                tol: float = 1e-10, max_iter: int = 5000, gauge_in_operator: bool | None = None):
+    """Plain FP64 method: equilibrate, block-Jacobi, GMRES(m); returns (x, result).
+
+    gauge_in_operator=None picks the penalty-free iteration + Coulomb
+    projection when delta_V = 0 and b is divergence-free (see module doc).
+    The returned result's relres is the true weighted residual of the gauged
+    system at the returned x.
+    """
     s = equilibration(sysm)
     P = BlockJacobi.build(sysm, xyz, block, scale=s)
-    res = gmres(lambda v: s * sysm.matvec(s * v), s * b, P.apply, m=m, tol=tol, max_iter=max_iter)
-    return s * res.x, res
+    if gauge_in_operator is None:
+        gauge_in_operator = not (sysm.delta_v == 0.0 and divergence_residual(sysm, b) <= 1e-10)
+    if gauge_in_operator:
+        res = gmres(lambda v: s * sysm.matvec(s * v), s * b, P.apply, m=m, tol=tol, max_iter=max_iter)
+        return s * res.x, res
+    M0 = sysm.matrix_no_gauge()
+    res = gmres(lambda v: s * (M0 @ (s * v)), s * b, P.apply, m=m, tol=tol, max_iter=max_iter)
+    x = coulomb_projection(sysm, s * res.x)
+    sb = s * b
+    res.relres = float(np.linalg.norm(s * (b - sysm.matvec(x))) / np.linalg.norm(sb)) if np.any(sb) else 0.0
+    res.converged = res.relres <= tol
+    return x, res

@@ -56,7 +56,8 @@ struct eddy_op {
   bool assembled = false;
   // static (uploaded at create)
   double* xyz;
-  int *tet, *region, *cidx, *edge_v, *comp;
+  int *tet, *region, *cidx, *edge_v, *comp, *edges, *cond_nodes;
+  std::vector<int32_t> is_cond;
   uint8_t* signbits;
   int *rowptr, *col, *diagpos, *cptr, *clist;
   int *wrowptr, *wcol, *wcptr, *wclist, *wtrowptr, *wtcol, *wtperm;
@@ -92,6 +93,8 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->signbits = c.take<uint8_t>(m->nt);
   o->edge_v = c.take<int>(m->ne * 2);
   o->comp = c.take<int>(m->nc);
+  o->edges = c.take<int>(m->ne * 2);
+  o->cond_nodes = c.take<int>(m->nc);
   o->rowptr = c.take<int>(m->ndof() + 1);
   o->col = c.take<int>(m->nnz());
   o->diagpos = c.take<int>(m->ndof());
@@ -153,10 +156,13 @@ eddy_status upload(T* dst, const std::vector<T>& src, hipStream_t st) {
   return EDDY_OK;
 }
 
-// y = M~ x (scaled system); `t` is the node-sized gauge temporary.
-void op_spmv(const eddy_op* o, const double2* x, const double2* b, double2* y, double2* t, hipStream_t st) {
-  launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, x, t, st);
-  launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, o->wrowptr, o->wcol, o->wval, t, x, b, y, st);
+// y = M~ x (scaled system; gauge term included if `gauge`); `t` is the
+// node-sized gauge temporary.
+void op_spmv(const eddy_op* o, const double2* x, const double2* b, double2* y, double2* t, hipStream_t st,
+             bool gauge = true) {
+  if (gauge) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, x, t, st);
+  launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, gauge ? o->wrowptr : nullptr, o->wcol, o->wval, t, x, b, y,
+              st);
 }
 
 }  // namespace
@@ -281,6 +287,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   o->nnz = m->nnz(); o->nnzw = m->nnzw(); o->nb = (int64_t)m->blk_ptr.size() - 1;
   o->nreg = m->nreg; o->ncomp = m->ncomp; o->bsize = p->block_size;
   o->tau = p->tau_gauge; o->delta_v = p->delta_v;
+  o->is_cond = m->is_cond;
   hipStream_t s = (hipStream_t)stream;
   std::vector<int32_t> blk_of(o->n), loc_of(o->n);
   for (int64_t k = 0; k < o->nb; ++k)
@@ -292,6 +299,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
 #define UP(dst, src) if (r == EDDY_OK) r = upload(dst, src, s)
   UP(o->xyz, m->xyz); UP(o->tet, m->tet); UP(o->region, m->region); UP(o->cidx, m->cidx);
   UP(o->signbits, m->signbits); UP(o->edge_v, m->edge_v); UP(o->comp, m->comp);
+  UP(o->edges, m->edges); UP(o->cond_nodes, m->cond_nodes);
   UP(o->rowptr, m->rowptr); UP(o->col, m->col); UP(o->diagpos, m->diagpos); UP(o->cptr, m->cptr);
   UP(o->clist, m->clist); UP(o->wrowptr, m->wrowptr); UP(o->wcol, m->wcol); UP(o->wcptr, m->wcptr);
   UP(o->wclist, m->wclist); UP(o->wtrowptr, m->wtrowptr); UP(o->wtcol, m->wtcol); UP(o->wtperm, m->wtperm);
@@ -313,8 +321,13 @@ void eddy_op_destroy(eddy_op* o) { delete o; }
 eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, double omega, eddy_stream stream) {
   if (!o || !nu || !sigma) { set_error("NULL argument"); return EDDY_ERR_ARG; }
   if (!(omega > 0)) { set_error("omega must be > 0"); return EDDY_ERR_ARG; }
-  for (int r = 0; r < o->nreg; ++r)
+  for (int r = 0; r < o->nreg; ++r) {
     if (!(nu[r] > 0) || !(sigma[r] >= 0)) { set_error("nu must be > 0 and sigma >= 0"); return EDDY_ERR_ARG; }
+    if ((sigma[r] > 0) != (o->is_cond[r] != 0)) {
+      set_error("sigma must be > 0 exactly on the regions flagged conducting at eddy_mesh_create");
+      return EDDY_ERR_ARG;
+    }
+  }
   hipStream_t s = (hipStream_t)stream;
   o->omega = omega;
   HIP_TRY(hipMemcpyAsync(o->nu_reg, nu, sizeof(double) * o->nreg, hipMemcpyHostToDevice, s));
@@ -402,9 +415,20 @@ namespace {
 struct SolveWs {
   double2 *V, *w, *z, *xt, *bt, *hd, *h1, *h2, *yd, *part;
   double *rpart, *nrm;
+  // Coulomb projection (nodal CG)
+  double2 *psi, *cr, *cz, *cp, *cq, *cg, *cs;
+  double* cdiag;
 };
-size_t carve_solve(SolveWs* w, void* base, int64_t n, int m) {
+size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne) {
   Carve c(base);
+  w->psi = c.take<double2>(nv);
+  w->cr = c.take<double2>(nv);
+  w->cz = c.take<double2>(nv);
+  w->cp = c.take<double2>(nv);
+  w->cq = c.take<double2>(nv);
+  w->cg = c.take<double2>(ne);
+  w->cs = c.take<double2>(8);
+  w->cdiag = c.take<double>(nv);
   w->V = c.take<double2>((int64_t)(m + 1) * n);
   w->w = c.take<double2>(n);
   w->z = c.take<double2>(n);
@@ -433,7 +457,7 @@ eddy_status eddy_solve_workspace_bytes(const eddy_op* o, const eddy_solve_opts* 
   eddy_status st = check_opts(opts);
   if (st != EDDY_OK) return st;
   SolveWs w;
-  *bytes = carve_solve(&w, nullptr, o->n, opts->restart);
+  *bytes = carve_solve(&w, nullptr, o->n, opts->restart, o->nv, o->ne);
   return EDDY_OK;
 }
 
@@ -447,12 +471,12 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   const int m = opts->restart;
   const int64_t n = o->n;
   SolveWs W;
-  const size_t need = carve_solve(&W, nullptr, n, m);
+  const size_t need = carve_solve(&W, nullptr, n, m, o->nv, o->ne);
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) {
     set_error("solve workspace too small or misaligned: need " + std::to_string(need) + " bytes");
     return EDDY_ERR_WORKSPACE;
   }
-  carve_solve(&W, ws, n, m);
+  carve_solve(&W, ws, n, m, o->nv, o->ne);
   hipStream_t s = (hipStream_t)stream;
   using cd = std::complex<double>;
   double hbuf[8];
@@ -462,14 +486,32 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
     *out = hbuf[0];
     return EDDY_OK;
   };
+  eddy_solve_report R{};
+  // Operator choice.  With delta_V = 0 and a divergence-free source (G^T b_A
+  // = 0), the gauged solution satisfies W^T A = 0, so the penalty term is
+  // zero at the solution: iterate on the penalty-free operator (singular but
+  // consistent, kernel {(G psi, -i omega psi|_c)}), keep the gauged blocks in
+  // the preconditioner, and restore the Coulomb gauge by projection below.
+  bool gauge_op = o->delta_v != 0.0;
+  {
+    launch_norm2(n, (const double2*)b_dev, W.rpart, W.nrm, s);
+    double braw = 0;
+    if ((st = read_norm(&braw)) != EDDY_OK) return st;
+    if (!std::isfinite(braw)) { set_error("right-hand side is not finite"); return EDDY_ERR_ARG; }
+    launch_edge_divergence(o->nv, o->wtrowptr, o->wtcol, o->edges, (const double2*)b_dev, W.cr, s);
+    launch_norm2(o->nv, W.cr, W.rpart, W.nrm, s);
+    double dnorm = 0;
+    if ((st = read_norm(&dnorm)) != EDDY_OK) return st;
+    R.div_residual = braw > 0 ? dnorm / braw : 0.0;
+    if (R.div_residual > 1e-10) gauge_op = true;
+  }
+  R.gauge_in_operator = gauge_op ? 1 : 0;
   // equilibrated right-hand side b~ = s b, x~ = 0
   launch_diag_scale(n, (const double2*)b_dev, o->s, 0, W.bt, s);
   launch_zero(n, W.xt, s);
   launch_norm2(n, W.bt, W.rpart, W.nrm, s);
   double bnorm = 0;
   if ((st = read_norm(&bnorm)) != EDDY_OK) return st;
-  eddy_solve_report R{};
-  if (!std::isfinite(bnorm)) { set_error("right-hand side is not finite"); return EDDY_ERR_ARG; }
   double beta = bnorm;
   int it = 0;
   std::vector<cd> H((m + 1) * m), g(m + 1), sn(m), y(m);
@@ -489,10 +531,10 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
         if (o->profile) (void)hipEventRecord(o->ev[0], s);
         launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, vj, W.z, s);
         if (o->profile) (void)hipEventRecord(o->ev[1], s);
-        launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, W.z, o->tvec, s);
+        if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, W.z, o->tvec, s);
         if (o->profile) (void)hipEventRecord(o->ev[2], s);
-        launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, o->wrowptr, o->wcol, o->wval, o->tvec, W.z, nullptr, W.w,
-                    s);
+        launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, gauge_op ? o->wrowptr : nullptr, o->wcol, o->wval,
+                    o->tvec, W.z, nullptr, W.w, s);
         if (o->profile) (void)hipEventRecord(o->ev[3], s);
         // CGS2
         launch_mdot(n, W.V, n, j + 1, W.w, W.part, s);
@@ -511,7 +553,7 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
         if (o->profile) {
           for (int c = 0; c < 4; ++c) {
             float ms = 0;
-            if (hipEventElapsedTime(&ms, o->ev[c], o->ev[c + 1]) == hipSuccess) {
+            if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, o->ev[c], o->ev[c + 1]) == hipSuccess) {
               o->prof_ms[c] += ms;
               o->prof_n[c] += 1;
             }
@@ -561,8 +603,8 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
       launch_combine(n, W.V, n, k, W.yd, W.w, s);
       launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, W.w, W.z, s);
       launch_axpy(n, W.z, W.xt, s);
-      // true residual r = b~ - M~ x~
-      op_spmv(o, W.xt, W.bt, W.w, o->tvec, s);
+      // true residual r = b~ - M~ x~ of the iterated operator
+      op_spmv(o, W.xt, W.bt, W.w, o->tvec, s, gauge_op);
       launch_norm2(n, W.w, W.rpart, W.nrm, s);
       if ((st = read_norm(&beta)) != EDDY_OK) return st;
       HIP_TRY(hipStreamSynchronize(s));   // yv must outlive its copy
@@ -575,8 +617,56 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   } else {
     R.relres = 0;
   }
-  // x = s x~, then remove the mass-weighted V mean per conductor component
+  // x = s x~
   launch_diag_scale(n, W.xt, o->s, 0, (double2*)x_dev, s);
+  if (!gauge_op && bnorm > 0) {
+    // Coulomb projection: (W^T G) psi = W^T A by Jacobi-preconditioned CG on
+    // the nodes (W^T A = W~^T x~), then A -= G psi, V += i omega psi|_c.
+    const int64_t nv = o->nv;
+    launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, W.xt, W.cr, s);
+    launch_lap_diag(nv, o->wtrowptr, o->wtcol, o->wtval, o->edges, o->s, W.cdiag, s);
+    launch_zero(nv, W.psi, s);
+    launch_norm2(nv, W.cr, W.rpart, W.nrm, s);
+    double r0 = 0;
+    if ((st = read_norm(&r0)) != EDDY_OK) return st;
+    if (r0 > 0) {
+      launch_jacobi(nv, W.cr, W.cdiag, W.cz, s);
+      HIP_TRY(hipMemcpyAsync(W.cp, W.cz, sizeof(double2) * nv, hipMemcpyDeviceToDevice, s));
+      launch_mdot(nv, W.cr, nv, 1, W.cz, W.part, s);
+      launch_reduce_cols(1, W.part, W.cs + 0, s);
+      int cur = 0;
+      const int kMaxCg = 20000;
+      for (int ci = 1; ci <= kMaxCg; ++ci) {
+        launch_grad_scaled(o->ne, o->edges, W.cp, o->s, W.cg, s);
+        launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, W.cg, W.cq, s);
+        launch_mdot(nv, W.cp, nv, 1, W.cq, W.part, s);
+        launch_reduce_cols(1, W.part, W.cs + 2, s);
+        launch_cg_step(nv, W.cs + cur, W.cs + 2, W.cp, W.cq, W.psi, W.cr, s);
+        launch_jacobi(nv, W.cr, W.cdiag, W.cz, s);
+        launch_mdot(nv, W.cr, nv, 1, W.cz, W.part, s);
+        launch_reduce_cols(1, W.part, W.cs + (1 - cur), s);
+        launch_cg_dir(nv, W.cs + (1 - cur), W.cs + cur, W.cz, W.cp, s);
+        cur = 1 - cur;
+        R.cg_iters = ci;
+        if (ci % 25 == 0 || ci == kMaxCg) {
+          launch_norm2(nv, W.cr, W.rpart, W.nrm, s);
+          double rn = 0;
+          if ((st = read_norm(&rn)) != EDDY_OK) return st;
+          if (!(rn > 1e-13 * r0)) break;
+        }
+      }
+      launch_project(o->ne, o->nc, o->edges, o->cond_nodes, W.psi, o->omega, (double2*)x_dev, s);
+    }
+  }
+  // true weighted residual of the gauged system at the returned x
+  if (bnorm > 0) {
+    launch_diag_scale(n, (const double2*)x_dev, o->s, 1, W.xt, s);
+    op_spmv(o, W.xt, W.bt, W.w, o->tvec, s, true);
+    launch_norm2(n, W.w, W.rpart, W.nrm, s);
+    if ((st = read_norm(&beta)) != EDDY_OK) return st;
+    R.relres = beta / bnorm;
+  }
+  // remove the mass-weighted V mean per conductor component
   launch_vmean(o->nc, o->ncomp, o->comp, o->lumped, (double2*)x_dev + o->ne, o->red, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));

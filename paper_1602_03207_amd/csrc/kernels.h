@@ -54,6 +54,20 @@ void launch_zero(int64_t n, double2* x, hipStream_t st);
 void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, double2* V, double2* scratch,
                   hipStream_t st);
 void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st);
+// Coulomb projection helpers (Poisson solve on W^T G by Jacobi-CG, then the shift)
+void launch_edge_divergence(int64_t nv, const int* wtrowptr, const int* wtcol, const int* edges, const double2* b,
+                            double2* d, hipStream_t st);
+void launch_lap_diag(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const int* edges,
+                     const double* s, double* diag, hipStream_t st);
+void launch_grad_scaled(int64_t ne, const int* edges, const double2* psi, const double* s, double2* g,
+                        hipStream_t st);
+void launch_cg_step(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q, double2* psi,
+                    double2* r, hipStream_t st);
+void launch_jacobi(int64_t n, const double2* r, const double* diag, double2* z, hipStream_t st);
+void launch_cg_dir(int64_t n, const double2* rz_new, const double2* rz_old, const double2* z, double2* p,
+                   hipStream_t st);
+void launch_project(int64_t ne, int64_t nc, const int* edges, const int* cond_nodes, const double2* psi, double omega,
+                    double2* x, hipStream_t st);
 void launch_edge_field(int64_t ne, const int* edge_v, const double2* x, double omega, double2* E, hipStream_t st);
 
 }  // namespace eddy

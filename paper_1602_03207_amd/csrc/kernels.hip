@@ -412,8 +412,102 @@ __global__ __launch_bounds__(kThreads) void k_wt(int64_t nv, const int* __restri
     acc.y += __shfl_xor(acc.y, o, kLanes);
   }
   if (row < nv && lane == 0) {
-    const double f = d0tau[row];
+    const double f = d0tau ? d0tau[row] : 1.0;
     t[row] = make_double2(acc.x * f, acc.y * f);
+  }
+}
+
+// d_n = (G^T b)_n = sum over edges e incident to n of (+b_e if n = hi(e), -b_e if n = lo(e));
+// the incident edges are found in node n's row of W~^T (edges sharing a tet with n).
+__global__ __launch_bounds__(kThreads) void k_edge_divergence(int64_t nv, const int* __restrict__ wtrowptr,
+                                                              const int* __restrict__ wtcol,
+                                                              const int* __restrict__ edges,
+                                                              const double2* __restrict__ b, double2* __restrict__ d) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nv) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q = wtrowptr[n]; q < wtrowptr[n + 1]; ++q) {
+    const int e = wtcol[q];
+    const int lo = edges[2 * e], hi = edges[2 * e + 1];
+    if (hi == n) acc = cadd(acc, b[e]);
+    else if (lo == n) acc = csub(acc, b[e]);
+  }
+  d[n] = acc;
+}
+
+// diag(W^T G)_n = sum_{e incident to n} W_en G_en, with W_en = W~_en / s_e
+__global__ __launch_bounds__(kThreads) void k_lap_diag(int64_t nv, const int* __restrict__ wtrowptr,
+                                                       const int* __restrict__ wtcol,
+                                                       const double* __restrict__ wtval,
+                                                       const int* __restrict__ edges, const double* __restrict__ s,
+                                                       double* __restrict__ diag) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nv) return;
+  double acc = 0.0;
+  for (int q = wtrowptr[n]; q < wtrowptr[n + 1]; ++q) {
+    const int e = wtcol[q];
+    const int lo = edges[2 * e], hi = edges[2 * e + 1];
+    if (hi == n) acc += wtval[q] / s[e];
+    else if (lo == n) acc -= wtval[q] / s[e];
+  }
+  diag[n] = acc;
+}
+
+// g_e = (psi_hi - psi_lo) / s_e  (gradient, pre-divided for the scaled W~^T)
+__global__ __launch_bounds__(kThreads) void k_grad_scaled(int64_t ne, const int* __restrict__ edges,
+                                                          const double2* __restrict__ psi,
+                                                          const double* __restrict__ s, double2* __restrict__ g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double2 d = csub(psi[edges[2 * e + 1]], psi[edges[2 * e]]);
+  const double f = 1.0 / s[e];
+  g[e] = make_double2(d.x * f, d.y * f);
+}
+
+// CG, step 1: alpha = rz / (p^H q); psi += alpha p; r -= alpha q   (rz, pq real parts on device)
+__global__ __launch_bounds__(kThreads) void k_cg_step(int64_t n, const double2* __restrict__ rz,
+                                                      const double2* __restrict__ pq, const double2* __restrict__ p,
+                                                      const double2* __restrict__ q, double2* __restrict__ psi,
+                                                      double2* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double den = pq[0].x;
+  const double a = den != 0.0 ? rz[0].x / den : 0.0;
+  psi[i] = rfma(a, p[i], psi[i]);
+  r[i] = rfma(-a, q[i], r[i]);
+}
+
+// z = r / diag
+__global__ __launch_bounds__(kThreads) void k_jacobi(int64_t n, const double2* __restrict__ r,
+                                                     const double* __restrict__ diag, double2* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double f = diag[i] != 0.0 ? 1.0 / diag[i] : 0.0;
+  z[i] = make_double2(r[i].x * f, r[i].y * f);
+}
+
+// p = z + (rz_new / rz_old) p
+__global__ __launch_bounds__(kThreads) void k_cg_dir(int64_t n, const double2* __restrict__ rz_new,
+                                                     const double2* __restrict__ rz_old,
+                                                     const double2* __restrict__ z, double2* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double den = rz_old[0].x;
+  const double bta = den != 0.0 ? rz_new[0].x / den : 0.0;
+  p[i] = rfma(bta, p[i], z[i]);
+}
+
+// Coulomb projection: A_e -= psi_hi - psi_lo;  V_c += i omega psi(node c)
+__global__ __launch_bounds__(kThreads) void k_project(int64_t ne, int64_t nc, const int* __restrict__ edges,
+                                                      const int* __restrict__ cond_nodes,
+                                                      const double2* __restrict__ psi, double omega,
+                                                      double2* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ne) {
+    x[i] = csub(x[i], csub(psi[edges[2 * i + 1]], psi[edges[2 * i]]));
+  } else if (i < ne + nc) {
+    const double2 q = psi[cond_nodes[i - ne]];
+    x[i] = cadd(x[i], make_double2(-omega * q.y, omega * q.x));
   }
 }
 
@@ -428,7 +522,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int64_t n, int64_t ne, const 
   double2 acc = make_double2(0.0, 0.0);
   if (row < n) {
     for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) acc = cfma(val[p], x[col[p]], acc);
-    if (row < ne)
+    if (wrowptr && row < ne)
       for (int p = wrowptr[row] + lane; p < wrowptr[row + 1]; p += kLanes) acc = rfma(wval[p], t[wcol[p]], acc);
   }
   for (int o = kLanes / 2; o > 0; o >>= 1) {
@@ -741,6 +835,33 @@ void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, 
 void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st) {
   k_udot_partial<<<kRedBlocks, kThreads, 0, st>>>(n, a, b, partial);
   k_reduce_cols<<<1, kThreads, 0, st>>>(partial, out);
+}
+void launch_edge_divergence(int64_t nv, const int* wtrowptr, const int* wtcol, const int* edges, const double2* b,
+                            double2* d, hipStream_t st) {
+  k_edge_divergence<<<blocks_for(nv), kThreads, 0, st>>>(nv, wtrowptr, wtcol, edges, b, d);
+}
+void launch_lap_diag(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const int* edges,
+                     const double* s, double* diag, hipStream_t st) {
+  k_lap_diag<<<blocks_for(nv), kThreads, 0, st>>>(nv, wtrowptr, wtcol, wtval, edges, s, diag);
+}
+void launch_grad_scaled(int64_t ne, const int* edges, const double2* psi, const double* s, double2* g,
+                        hipStream_t st) {
+  k_grad_scaled<<<blocks_for(ne), kThreads, 0, st>>>(ne, edges, psi, s, g);
+}
+void launch_cg_step(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q, double2* psi,
+                    double2* r, hipStream_t st) {
+  k_cg_step<<<blocks_for(n), kThreads, 0, st>>>(n, rz, pq, p, q, psi, r);
+}
+void launch_jacobi(int64_t n, const double2* r, const double* diag, double2* z, hipStream_t st) {
+  k_jacobi<<<blocks_for(n), kThreads, 0, st>>>(n, r, diag, z);
+}
+void launch_cg_dir(int64_t n, const double2* rz_new, const double2* rz_old, const double2* z, double2* p,
+                   hipStream_t st) {
+  k_cg_dir<<<blocks_for(n), kThreads, 0, st>>>(n, rz_new, rz_old, z, p);
+}
+void launch_project(int64_t ne, int64_t nc, const int* edges, const int* cond_nodes, const double2* psi, double omega,
+                    double2* x, hipStream_t st) {
+  k_project<<<blocks_for(ne + nc), kThreads, 0, st>>>(ne, nc, edges, cond_nodes, psi, omega, x);
 }
 void launch_edge_field(int64_t ne, const int* edge_v, const double2* x, double omega, double2* E, hipStream_t st) {
   k_edge_field<<<blocks_for(ne), kThreads, 0, st>>>(ne, edge_v, x, omega, E);

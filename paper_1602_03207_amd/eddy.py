@@ -32,7 +32,8 @@ class _Opts(C.Structure):
 class _Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("relres", C.c_double), ("est_relres", C.c_double),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("gauge_in_operator", C.c_int32), ("cg_iters", C.c_int32),
+                ("div_residual", C.c_double)]
 
 
 EXPORTS = [
@@ -169,6 +170,9 @@ class SolveReport:
     relres: float
     est_relres: float
     seconds: float
+    gauge_in_operator: bool = False
+    cg_iters: int = 0
+    div_residual: float = 0.0
 
 
 def _aligned(nbytes: int, device):
@@ -235,7 +239,8 @@ class Operator:
         st = _check(_lib.eddy_solve(self._h, _dev(b), _dev(x), C.byref(opts), self._solve_ws[1], self._solve_ws[2],
                                     C.byref(rep), _stream()), "eddy_solve")
         return x, SolveReport(rep.iters, rep.restarts, bool(rep.converged), bool(rep.breakdown), rep.relres,
-                              rep.est_relres, rep.seconds)
+                              rep.est_relres, rep.seconds, bool(rep.gauge_in_operator), rep.cg_iters,
+                              rep.div_residual)
 
     def spmv(self, x, out=None):
         y = self._c128() if out is None else out

@@ -206,3 +206,25 @@ def test_solve_reports_nonconvergence_and_zero_rhs():
     z = torch.zeros_like(b)
     x, rep = op.solve(z, tol=1e-10)
     assert rep.converged and torch.count_nonzero(x) == 0
+
+
+def test_gauge_modes_and_coulomb_projection():
+    """Divergence-free source: penalty-free iteration + projection, W^T A = 0.
+    Non-solenoidal source: the gauged operator is iterated.  Both match the
+    oracle's direct solve of the gauged system."""
+    from oracle.solve import direct
+    from oracle.post import remove_v_mean
+    m, s, op, J = case("c1")
+    b = op.rhs_from_current(torch.from_numpy(J).cuda())
+    x, rep = op.solve(b, tol=1e-12)
+    assert rep.converged and not rep.gauge_in_operator and rep.div_residual < 1e-13 and rep.cg_iters > 0
+    xn = x.cpu().numpy()
+    A = xn[: op.ne]
+    assert np.linalg.norm(s.W.T @ A) <= 1e-10 * np.linalg.norm(s.W.T @ np.abs(A))
+    rng = np.random.default_rng(7)
+    Jr = rng.normal(size=(m.nt, 3))
+    b2 = op.rhs_from_current(torch.from_numpy(Jr).cuda())
+    x2, rep2 = op.solve(b2, tol=1e-12, max_iter=5000)
+    assert rep2.gauge_in_operator and rep2.div_residual > 1e-6 and rep2.converged
+    xo = remove_v_mean(s, direct(s, s.rhs(Jr)))
+    assert np.linalg.norm(x2.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)

@@ -81,3 +81,21 @@ def test_rcb_partition_invariants():
         assert sizes.min() >= bsz // 4
         for blk in blocks:
             assert np.all(np.diff(blk) > 0)
+
+
+def test_penalty_free_iteration_returns_the_gauged_solution():
+    """GMRES on the operator without the gauge term, then the Coulomb
+    projection, gives the gauged system's solution (delta_V = 0,
+    divergence-free b); iterating on the gauged operator agrees."""
+    from oracle.solve import coulomb_projection, divergence_residual
+    m, s, b = sys_for(4)
+    assert divergence_residual(s, b) < 1e-13
+    xd = remove_v_mean(s, direct(s, b))
+    x0, r0 = solve_gmres(s, m.xyz, b, block=32, tol=1e-13, gauge_in_operator=False)
+    x1, r1 = solve_gmres(s, m.xyz, b, block=32, tol=1e-13, gauge_in_operator=True)
+    for x in (x0, x1):
+        assert np.linalg.norm(remove_v_mean(s, x) - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert np.linalg.norm(s.W.T @ x0[: s.topo.ne]) <= 1e-12 * np.linalg.norm(s.W.T @ np.abs(x0[: s.topo.ne]))
+    # the projection is idempotent and only moves along the kernel
+    y = coulomb_projection(s, x0)
+    assert np.linalg.norm(y - x0) <= 1e-10 * np.linalg.norm(x0)
