@@ -35,20 +35,32 @@ void launch_rhs_elem(int64_t nt, const double* xyz, const int* tet, const uint8_
 // ---- solve
 void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const double* d0tau,
                const double2* x, double2* t, hipStream_t st);
-// y = M~ x + W~ t  (A rows); if b != nullptr: y = b - (...)
-void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const double2* val, const int* wrowptr,
-                 const int* wcol, const double* wval, const double2* t, const double2* x, const double2* b,
-                 double2* y, hipStream_t st);
-void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const double2* minv, const double2* r,
-                        double2* z, hipStream_t st);
-void launch_mdot(int64_t n, const double2* V, int64_t ldv, int q, const double2* w, double2* partial, hipStream_t st);
+// y = M~ x + W~ t  (A rows, if wrowptr); if b != nullptr: y = b - (...).
+// T = double2 (complex128) or float2 (complex64) storage and arithmetic.
+template <class T>
+void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const T* val, const int* wrowptr,
+                 const int* wcol, const double* wval, const double2* t, const T* x, const double2* b, T* y,
+                 hipStream_t st);
+template <class T>
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, const T* r, T* z,
+                        hipStream_t st);
+// Krylov primitives: storage T, all reductions and Hessenberg entries in FP64
+template <class T>
+void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st);
 void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st);
-void launch_update(int64_t n, const double2* V, int64_t ldv, int q, const double2* h, double2* w, hipStream_t st);
-void launch_norm2(int64_t n, const double2* w, double* partial, double* out_norm, hipStream_t st);
-void launch_scale_by_inv(int64_t n, const double2* w, const double* norm, double2* v, hipStream_t st);
-void launch_scale_host(int64_t n, const double2* w, double a, double2* v, hipStream_t st);
-void launch_combine(int64_t n, const double2* V, int64_t ldv, int q, const double2* y, double2* u, hipStream_t st);
-void launch_axpy(int64_t n, const double2* z, double2* x, hipStream_t st);
+template <class T>
+void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, hipStream_t st);
+template <class T>
+void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipStream_t st);
+template <class T>
+void launch_scale_by_inv(int64_t n, const T* w, const double* norm, T* v, hipStream_t st);
+template <class Ti, class To>
+void launch_scale_host(int64_t n, const Ti* w, double a, To* v, hipStream_t st);
+template <class T>
+void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y, T* u, hipStream_t st);
+template <class T>
+void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st);
+void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st);
 void launch_zero(int64_t n, double2* x, hipStream_t st);
 void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, double2* V, double2* scratch,

@@ -267,12 +267,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_block_invert(
     int* __restrict__ status) {
   __shared__ double2 A[kMaxBlock * kMaxBlock];   // A(i, j) at j * 64 + i
   __shared__ int perm[kMaxBlock];
+  __shared__ int wn[kMaxBlock][kMaxWRow];         // nodes of W~ row i
+  __shared__ double wv[kMaxBlock][kMaxWRow];      // W~_in
+  __shared__ double wd[kMaxBlock][kMaxWRow];      // W~_in tau / D0_n
+  __shared__ int wc[kMaxBlock];
   const int k = blockIdx.x;
   const int i = threadIdx.x;
   const int b0 = blk_ptr[k];
   const int sz = blk_ptr[k + 1] - b0;
   for (int j = 0; j < kMaxBlock; ++j) A[j * kMaxBlock + i] = make_double2(0.0, 0.0);
-  __syncthreads();
+  int cnt = 0;
   if (i < sz) {
     const int r = blk_dofs[b0 + i];
     for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
@@ -280,14 +284,28 @@ __global__ __launch_bounds__(kMaxBlock) void k_block_invert(
       if (blk_of[c] == k) A[loc_of[c] * kMaxBlock + i] = val[p];
     }
     if (r < ne) {
-      for (int p = wrowptr[r]; p < wrowptr[r + 1]; ++p) {
-        const int nn = wcol[p];
-        const double f = wval[p] * d0tau[nn];
-        for (int q = wtrowptr[nn]; q < wtrowptr[nn + 1]; ++q) {
-          const int c = wtcol[q];
-          if (blk_of[c] == k) A[loc_of[c] * kMaxBlock + i].x += f * wtval[q];
-        }
+      cnt = wrowptr[r + 1] - wrowptr[r];      // <= kMaxWRow, checked on the host
+      for (int q = 0; q < cnt; ++q) {
+        const int nq = wcol[wrowptr[r] + q];
+        wn[i][q] = nq;
+        wv[i][q] = wval[wrowptr[r] + q];
+        wd[i][q] = wval[wrowptr[r] + q] * d0tau[nq];
       }
+    }
+  }
+  wc[i] = cnt;
+  __syncthreads();
+  // gauge block tau (W~ D0^-1 W~^T)_ij = sum over shared nodes n of W~_in W~_jn tau / D0_n
+  if (cnt > 0) {
+    for (int j = 0; j < sz; ++j) {
+      const int cj = wc[j];
+      double acc = 0.0;
+      for (int q = 0; q < cnt; ++q) {
+        const int nq = wn[i][q];
+        for (int u = 0; u < cj; ++u)
+          if (wn[j][u] == nq) acc += wd[i][q] * wv[j][u];
+      }
+      A[j * kMaxBlock + i].x += acc;
     }
   }
   __syncthreads();
@@ -511,33 +529,57 @@ __global__ __launch_bounds__(kThreads) void k_project(int64_t ne, int64_t nc, co
   }
 }
 
+// ---- storage-type helpers: complex128 (double2) or complex64 (float2) ----
+__device__ __forceinline__ double2 ld2(double2 a) { return a; }
+__device__ __forceinline__ double2 ld2(float2 a) { return make_double2(a.x, a.y); }
+template <class T> __device__ __forceinline__ T st2(double2 a);
+template <> __device__ __forceinline__ double2 st2<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 st2<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+template <class T> __device__ __forceinline__ T zero2();
+template <> __device__ __forceinline__ double2 zero2<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float2 zero2<float2>() { return make_float2(0.f, 0.f); }
+// acc + a * b in the storage precision
+template <class T> __device__ __forceinline__ T cfmaT(T a, T b, T acc) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+  return acc;
+}
+
+// y = M~ x (+ W~ t on A rows if wrowptr), 8 lanes per row; y = b - (...) if b.
+// Arithmetic in the storage precision T.
+template <class T>
 __global__ __launch_bounds__(kThreads) void k_spmv(int64_t n, int64_t ne, const int* __restrict__ rowptr,
-                                                   const int* __restrict__ col, const double2* __restrict__ val,
+                                                   const int* __restrict__ col, const T* __restrict__ val,
                                                    const int* __restrict__ wrowptr, const int* __restrict__ wcol,
                                                    const double* __restrict__ wval, const double2* __restrict__ t,
-                                                   const double2* __restrict__ x, const double2* __restrict__ b,
-                                                   double2* __restrict__ y) {
+                                                   const T* __restrict__ x, const double2* __restrict__ b,
+                                                   T* __restrict__ y) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
   const int lane = threadIdx.x % kLanes;
-  double2 acc = make_double2(0.0, 0.0);
+  T acc = zero2<T>();
   if (row < n) {
-    for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) acc = cfma(val[p], x[col[p]], acc);
-    if (wrowptr && row < ne)
-      for (int p = wrowptr[row] + lane; p < wrowptr[row + 1]; p += kLanes) acc = rfma(wval[p], t[wcol[p]], acc);
+    for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) acc = cfmaT(val[p], x[col[p]], acc);
+    if (wrowptr && row < ne) {
+      double2 ga = make_double2(0.0, 0.0);
+      for (int p = wrowptr[row] + lane; p < wrowptr[row + 1]; p += kLanes) ga = rfma(wval[p], t[wcol[p]], ga);
+      acc.x += ga.x;
+      acc.y += ga.y;
+    }
   }
   for (int o = kLanes / 2; o > 0; o >>= 1) {
     acc.x += __shfl_xor(acc.x, o, kLanes);
     acc.y += __shfl_xor(acc.y, o, kLanes);
   }
-  if (row < n && lane == 0) y[row] = b ? csub(b[row], acc) : acc;
+  if (row < n && lane == 0) y[row] = b ? st2<T>(csub(b[row], ld2(acc))) : acc;
 }
 
 // z_I = Minv_I r_I, one 64-lane wavefront per block, 4 blocks per workgroup.
+template <class T>
 __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int* __restrict__ blk_ptr,
                                                           const int* __restrict__ blk_dofs,
-                                                          const double2* __restrict__ minv,
-                                                          const double2* __restrict__ r, double2* __restrict__ z) {
-  __shared__ double2 rl[4][kMaxBlock];
+                                                          const T* __restrict__ minv, const T* __restrict__ r,
+                                                          T* __restrict__ z) {
+  __shared__ T rl[4][kMaxBlock];
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * 4 + w;
   int b0 = 0, sz = 0, dof = -1;
@@ -546,18 +588,19 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int*
     sz = blk_ptr[k + 1] - b0;
     if (i < sz) dof = blk_dofs[b0 + i];
   }
-  rl[w][i] = dof >= 0 ? r[dof] : make_double2(0.0, 0.0);
+  rl[w][i] = dof >= 0 ? r[dof] : zero2<T>();
   __syncthreads();
   if (dof < 0) return;
-  const double2* Mk = minv + k * kMaxBlock * kMaxBlock;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int j = 0; j < sz; ++j) acc = cfma(Mk[j * kMaxBlock + i], rl[w][j], acc);
+  const T* Mk = minv + k * kMaxBlock * kMaxBlock;
+  T acc = zero2<T>();
+  for (int j = 0; j < sz; ++j) acc = cfmaT(Mk[j * kMaxBlock + i], rl[w][j], acc);
   z[dof] = acc;
 }
 
-// partial[(c*8+k) * kRedBlocks + blockIdx.x] = sum_i conj(V_{c*8+k}[i]) w[i]
-__global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const double2* __restrict__ V, int64_t ldv, int q,
-                                                   const double2* __restrict__ w, double2* __restrict__ partial) {
+// partial[(c*8+k) * kRedBlocks + blockIdx.x] = sum_i conj(V_{c*8+k}[i]) w[i]  (FP64 accumulation)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                   const T* __restrict__ w, double2* __restrict__ partial) {
   __shared__ double sh[4];
   const int c0 = blockIdx.y * 8;
   const int cnt = min(8, q - c0);
@@ -565,10 +608,10 @@ __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const double2* __r
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[k] = make_double2(0.0, 0.0);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 wi = w[i];
+    const double2 wi = ld2(w[i]);
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (k < cnt) acc[k] = cfma_conj(V[(int64_t)(c0 + k) * ldv + i], wi, acc[k]);
+      if (k < cnt) acc[k] = cfma_conj(ld2(V[(int64_t)(c0 + k) * ldv + i]), wi, acc[k]);
   }
   for (int k = 0; k < cnt; ++k) {
     const double re = block_sum(acc[k].x, sh);
@@ -592,30 +635,32 @@ __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restr
   if (threadIdx.x == 0) out[k] = make_double2(re, im);
 }
 
-// w -= sum_k V_k h_k
-__global__ __launch_bounds__(kThreads) void k_update(int64_t n, const double2* __restrict__ V, int64_t ldv, int q,
-                                                     const double2* __restrict__ h, double2* __restrict__ w) {
+// w -= sum_k V_k h_k  (FP64 arithmetic, stored in T)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_update(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                     const double2* __restrict__ h, T* __restrict__ w) {
   __shared__ double2 hs[kMaxRestart + 1];
   if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double2 acc = w[i];
+  double2 acc = ld2(w[i]);
   for (int k = 0; k < q; ++k) {
-    const double2 v = V[(int64_t)k * ldv + i];
+    const double2 v = ld2(V[(int64_t)k * ldv + i]);
     const double2 hk = hs[k];
     acc.x -= v.x * hk.x - v.y * hk.y;
     acc.y -= v.x * hk.y + v.y * hk.x;
   }
-  w[i] = acc;
+  w[i] = st2<T>(acc);
 }
 
-__global__ __launch_bounds__(kThreads) void k_norm2_partial(int64_t n, const double2* __restrict__ w,
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_norm2_partial(int64_t n, const T* __restrict__ w,
                                                             double* __restrict__ partial) {
   __shared__ double sh[4];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 v = w[i];
+    const double2 v = ld2(w[i]);
     acc = fma(v.x, v.x, fma(v.y, v.y, acc));
   }
   acc = block_sum(acc, sh);
@@ -631,39 +676,51 @@ __global__ __launch_bounds__(kThreads) void k_norm2_final(const double* __restri
   if (threadIdx.x == 0) out[0] = sqrt(acc);
 }
 
-__global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const double2* __restrict__ w,
-                                                           const double* __restrict__ nrm, double2* __restrict__ v) {
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const T* __restrict__ w,
+                                                           const double* __restrict__ nrm, T* __restrict__ v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double a = nrm[0];
   const double f = a > 0.0 ? 1.0 / a : 0.0;
-  const double2 x = w[i];
-  v[i] = make_double2(x.x * f, x.y * f);
+  const double2 x = ld2(w[i]);
+  v[i] = st2<T>(make_double2(x.x * f, x.y * f));
 }
 
-__global__ __launch_bounds__(kThreads) void k_scale_host(int64_t n, const double2* __restrict__ w, double a,
-                                                         double2* __restrict__ v) {
+template <class Ti, class To>
+__global__ __launch_bounds__(kThreads) void k_scale_host(int64_t n, const Ti* __restrict__ w, double a,
+                                                         To* __restrict__ v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double2 x = w[i];
-  v[i] = make_double2(x.x * a, x.y * a);
+  const double2 x = ld2(w[i]);
+  v[i] = st2<To>(make_double2(x.x * a, x.y * a));
 }
 
-__global__ __launch_bounds__(kThreads) void k_combine(int64_t n, const double2* __restrict__ V, int64_t ldv, int q,
-                                                      const double2* __restrict__ y, double2* __restrict__ u) {
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_combine(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                      const double2* __restrict__ y, T* __restrict__ u) {
   __shared__ double2 ys[kMaxRestart + 1];
   if (threadIdx.x < q) ys[threadIdx.x] = y[threadIdx.x];
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double2 acc = make_double2(0.0, 0.0);
-  for (int k = 0; k < q; ++k) acc = cfma(V[(int64_t)k * ldv + i], ys[k], acc);
-  u[i] = acc;
+  for (int k = 0; k < q; ++k) acc = cfma(ld2(V[(int64_t)k * ldv + i]), ys[k], acc);
+  u[i] = st2<T>(acc);
 }
 
-__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const double2* __restrict__ z, double2* __restrict__ x) {
+// x += z   (x FP64, z in storage type)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restrict__ z, double2* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = cadd(x[i], z[i]);
+  if (i < n) x[i] = cadd(x[i], ld2(z[i]));
+}
+
+// out = (complex64) in
+__global__ __launch_bounds__(kThreads) void k_to_c64(int64_t n, const double2* __restrict__ in,
+                                                     float2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
 }
 
 __global__ __launch_bounds__(kThreads) void k_diag_scale(int64_t n, const double2* __restrict__ in,
@@ -787,41 +844,67 @@ void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* 
                const double2* x, double2* t, hipStream_t st) {
   k_wt<<<blocks_for(nv * kLanes), kThreads, 0, st>>>(nv, wtrowptr, wtcol, wtval, d0tau, x, t);
 }
-void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const double2* val, const int* wrowptr,
-                 const int* wcol, const double* wval, const double2* t, const double2* x, const double2* b,
-                 double2* y, hipStream_t st) {
-  k_spmv<<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, ne, rowptr, col, val, wrowptr, wcol, wval, t, x, b, y);
+template <class T>
+void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const T* val, const int* wrowptr,
+                 const int* wcol, const double* wval, const double2* t, const T* x, const double2* b, T* y,
+                 hipStream_t st) {
+  k_spmv<T><<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, ne, rowptr, col, val, wrowptr, wcol, wval, t, x, b, y);
 }
-void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const double2* minv, const double2* r,
-                        double2* z, hipStream_t st) {
-  k_block_apply<<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
+template <class T>
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, const T* r, T* z,
+                        hipStream_t st) {
+  k_block_apply<T><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
 }
-void launch_mdot(int64_t n, const double2* V, int64_t ldv, int q, const double2* w, double2* partial, hipStream_t st) {
+template <class T>
+void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st) {
   dim3 grid(kRedBlocks, (q + 7) / 8);
-  k_mdot<<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial);
+  k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial);
 }
 void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st) {
   k_reduce_cols<<<q, kThreads, 0, st>>>(partial, out);
 }
-void launch_update(int64_t n, const double2* V, int64_t ldv, int q, const double2* h, double2* w, hipStream_t st) {
-  k_update<<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, h, w);
+template <class T>
+void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, hipStream_t st) {
+  k_update<T><<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, h, w);
 }
-void launch_norm2(int64_t n, const double2* w, double* partial, double* out_norm, hipStream_t st) {
-  k_norm2_partial<<<kRedBlocks, kThreads, 0, st>>>(n, w, partial);
+template <class T>
+void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipStream_t st) {
+  k_norm2_partial<T><<<kRedBlocks, kThreads, 0, st>>>(n, w, partial);
   k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm);
 }
-void launch_scale_by_inv(int64_t n, const double2* w, const double* norm, double2* v, hipStream_t st) {
-  k_scale_by_inv<<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v);
+template <class T>
+void launch_scale_by_inv(int64_t n, const T* w, const double* norm, T* v, hipStream_t st) {
+  k_scale_by_inv<T><<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v);
 }
-void launch_scale_host(int64_t n, const double2* w, double a, double2* v, hipStream_t st) {
-  k_scale_host<<<blocks_for(n), kThreads, 0, st>>>(n, w, a, v);
+template <class Ti, class To>
+void launch_scale_host(int64_t n, const Ti* w, double a, To* v, hipStream_t st) {
+  k_scale_host<Ti, To><<<blocks_for(n), kThreads, 0, st>>>(n, w, a, v);
 }
-void launch_combine(int64_t n, const double2* V, int64_t ldv, int q, const double2* y, double2* u, hipStream_t st) {
-  k_combine<<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, y, u);
+template <class T>
+void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y, T* u, hipStream_t st) {
+  k_combine<T><<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, y, u);
 }
-void launch_axpy(int64_t n, const double2* z, double2* x, hipStream_t st) {
-  k_axpy<<<blocks_for(n), kThreads, 0, st>>>(n, z, x);
+template <class T>
+void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
+  k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x);
 }
+void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
+  k_to_c64<<<blocks_for(n), kThreads, 0, st>>>(n, in, out);
+}
+#define EDDY_INST(T)                                                                                              \
+  template void launch_spmv<T>(int64_t, int64_t, const int*, const int*, const T*, const int*, const int*,        \
+                               const double*, const double2*, const T*, const double2*, T*, hipStream_t);         \
+  template void launch_block_apply<T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t);      \
+  template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t);                 \
+  template void launch_update<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);               \
+  template void launch_norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                \
+  template void launch_scale_by_inv<T>(int64_t, const T*, const double*, T*, hipStream_t);                        \
+  template void launch_scale_host<double2, T>(int64_t, const double2*, double, T*, hipStream_t);                  \
+  template void launch_combine<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);              \
+  template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);
+EDDY_INST(double2)
+EDDY_INST(float2)
+#undef EDDY_INST
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st) {
   k_diag_scale<<<blocks_for(n), kThreads, 0, st>>>(n, in, s, divide, out);
 }

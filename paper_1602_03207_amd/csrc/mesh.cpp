@@ -291,6 +291,11 @@ eddy_status build_mesh(eddy_mesh* m) {
     }
   };
   build_rows(ne, genW, m->wrowptr, m->wcol, m->wcptr, m->wclist);
+  for (int64_t r = 0; r < ne; ++r)
+    if (m->wrowptr[r + 1] - m->wrowptr[r] > kMaxWRow) {
+      set_error("an edge touches more than " + std::to_string(kMaxWRow) + " nodes through its tetrahedra");
+      return EDDY_ERR_MESH;
+    }
   group_by(m->wcol, nv, m->wtrowptr, m->wtperm);
   m->wtcol.resize(m->wcol.size());
   {
