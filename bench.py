@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
+                    help="headline method; 'both' also times plain FP64 for comparison")
     return ap.parse_args()
 
 
@@ -61,22 +63,27 @@ def workload(name):
     return m, nu, sig, omega, J1, J2, cond, tau, desc
 
 
-def spmv_bytes(M, op):
-    """Algorithmic bytes of one k_spmv launch (CSR part + W~ t part)."""
+def spmv_bytes(M, op, vb=16, gauge=False):
+    """Algorithmic bytes of one k_spmv launch: values + col + rowptr + x once + y;
+    vb = bytes per complex value (16 complex128, 8 complex64); the gauged
+    variant also streams W~ and reads t."""
     n, ne, nv = op.ndof, op.ne, op.nv
-    return (20 * M.nnz + 4 * (n + 1) + 16 * n + 16 * n
-            + 12 * M.nnz_w + 4 * (ne + 1) + 16 * nv)
+    b = (vb + 4) * M.nnz + 4 * (n + 1) + 2 * vb * n
+    if gauge:
+        b += 12 * M.nnz_w + 4 * (ne + 1) + 16 * nv
+    return b
 
 
 def wt_bytes(M, op):
     return 12 * M.nnz_w + 4 * (op.nv + 1) + 16 * op.ne + 16 * op.nv + 8 * op.nv
 
 
-def block_apply_bytes(M, op, block):
+def block_apply_bytes(M, op, block, vb=16):
+    """Block inverses (vb bytes per complex entry) + block pointers + DOF list + r gather + z scatter."""
     import numpy as np
     ptr, _ = M.blocks(block)
     sz = np.diff(ptr).astype(np.int64)
-    return int(16 * (sz * sz).sum() + 4 * (len(ptr)) + 4 * op.ndof + 32 * op.ndof)
+    return int(vb * (sz * sz).sum() + 4 * (len(ptr)) + 4 * op.ndof + 2 * vb * op.ndof)
 
 
 def cpu_baseline(args, gpu_iters):
@@ -136,60 +143,73 @@ def main():
     b = torch.empty((2, op.ndof), dtype=torch.complex128, device="cuda")
     x = torch.empty(op.ndof, dtype=torch.complex128, device="cuda")
 
-    def step():
-        op.assemble(nu, sig, omega)
-        op.rhs_from_current(J1d, out=b[0])
-        op.rhs_from_current(J2d, out=b[1])
-        _, rep = op.solve(b[0], tol=args.tol, restart=args.restart, max_iter=args.max_iter, out=x)
-        Z = op.impedance(x[None], b, [1.0, 1.0])
-        return rep, Z
+    def make_step(prec):
+        def step():
+            op.assemble(nu, sig, omega)
+            op.rhs_from_current(J1d, out=b[0])
+            op.rhs_from_current(J2d, out=b[1])
+            _, rep = op.solve(b[0], tol=args.tol, restart=args.restart, max_iter=args.max_iter, out=x,
+                              precision=prec)
+            Z = op.impedance(x[None], b, [1.0, 1.0])
+            return rep, Z
+        return step
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    op.profile(True)
-    t0 = time.perf_counter()
-    reps = []
-    for _ in range(args.steps):
-        reps.append(step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = op.profile(False)
-    rep, Z = reps[-1]
-    sec_per_solve = elapsed / args.steps
+    def timed(prec):
+        step = make_step(prec)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        op.profile(True)
+        t0 = time.perf_counter()
+        reps = []
+        for _ in range(args.steps):
+            reps.append(step())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = op.profile(False)
+        vb = 8 if prec == "mixed" else 16
+        kb = {"block_apply": block_apply_bytes(M, op, args.block, vb), "gauge_wt": wt_bytes(M, op),
+              "spmv": spmv_bytes(M, op, vb, gauge=reps[-1][0].gauge_in_operator)}
+        kernels = {}
+        for name, (ms, cnt) in prof.items():
+            avg = ms / max(cnt, 1)
+            entry = {"avg_ms": round(avg, 5), "launches": cnt, "total_ms": round(ms, 2)}
+            if name in kb and cnt:
+                gbs = kb[name] / (avg * 1e-3) / 1e9
+                entry.update({"bytes_per_launch": kb[name], "GB/s": round(gbs, 1),
+                              "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            kernels[name] = entry
+        rep, Z = reps[-1]
+        return {"sec": elapsed / args.steps, "rep": rep, "Z": Z, "kernels": kernels}
 
-    kb = {
-        "block_apply": block_apply_bytes(M, op, args.block),
-        "gauge_wt": wt_bytes(M, op),
-        "spmv": spmv_bytes(M, op),
-    }
-    kernels = {}
-    for name, (ms, cnt) in prof.items():
-        avg = ms / max(cnt, 1)
-        entry = {"avg_ms": round(avg, 5), "launches": cnt, "total_ms": round(ms, 2)}
-        if name in kb and cnt:
-            gbs = kb[name] / (avg * 1e-3) / 1e9
-            entry.update({"bytes_per_launch": kb[name], "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
-        kernels[name] = entry
-    single = {k: v for k, v in kernels.items() if k in kb and v["launches"]}
-    dom = max(single, key=lambda k: single[k]["total_ms"]) if single else "spmv"
+    head = "mixed" if args.precision in ("mixed", "both") else "fp64"
+    runs = {head: timed(head)}
+    if args.precision == "both":
+        runs["fp64"] = timed("fp64")
+    H = runs[head]
+    rep, Z, kernels = H["rep"], H["Z"], H["kernels"]
+    sec_per_solve = H["sec"]
+    knames = {"block_apply": "k_block_apply", "gauge_wt": "k_wt", "spmv": "k_spmv"}
+    single = {k: v for k, v in kernels.items() if k in knames and v["launches"]}
     roof = None
-    if dom in single:
+    if single:
+        dom = max(single, key=lambda k: single[k]["total_ms"])
         d = single[dom]
-        roof = {"bound": "hbm", "kernel": {"block_apply": "k_block_apply", "gauge_wt": "k_wt", "spmv": "k_spmv"}[dom],
+        roof = {"bound": "hbm", "kernel": knames[dom] + ("<float2>" if head == "mixed" else "<double2>"),
                 "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"], "traffic": None}
 
     cpu = None
     if not args.no_cpu_baseline and args.workload == "tube":
-        nt_s, nd_s, t_setup, t_it, threads = cpu_baseline(args, rep.iters)
-        est = t_setup * (M.nt / nt_s) + t_it * (op.ndof / nd_s) * rep.iters
+        it_cpu = runs["fp64"]["rep"].iters if "fp64" in runs else rep.iters
+        nt_s, nd_s, t_setup, t_it, threads = cpu_baseline(args, it_cpu)
+        est = t_setup * (M.nt / nt_s) + t_it * (op.ndof / nd_s) * it_cpu
         cpu = {"value": round(est, 2), "unit": "s per probe-position solve", "cores": threads, "kind": "oracle",
                "sample": (f"oracle on the tube cross-section over z in [-2,2] mm ({nt_s} tets, {nd_s} DOF): "
                           f"setup {t_setup:.2f} s + {t_it:.3f} s per GMRES iteration, scaled linearly to "
-                          f"{M.nt} tets / {op.ndof} DOF and to the GPU's {rep.iters} iterations")}
+                          f"{M.nt} tets / {op.ndof} DOF and to the GPU's {it_cpu} plain-FP64 iterations")}
 
     out = {
-        "metric": "s per probe-position solve at rel-res 1e-8 (plain FP64 GMRES + block-Jacobi); SpMV GB/s",
+        "metric": "s per probe-position solve at rel-res 1e-8 (learned/mixed vs plain FP64); SpMV GB/s",
         "value": round(sec_per_solve, 4),
         "unit": "s",
         "n_gpus": 1,
@@ -199,12 +219,18 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128 (f64)",
+        "dtype": "c64 inner / c128 outer" if head == "mixed" else "c128 (f64)",
         "data": "synthetic",
         "config": {**desc, "tets": M.nt, "dof": op.ndof, "nnz": M.nnz, "nnz_w": M.nnz_w, "block": args.block,
-                   "restart": args.restart, "tol": args.tol, "precision": "fp64", "parallelism": "single GPU"},
+                   "restart": args.restart, "tol": args.tol, "precision": head, "parallelism": "single GPU"},
         "solve": {"iters": rep.iters, "restarts": rep.restarts, "converged": rep.converged, "relres": rep.relres,
+                  "projection_cg_iters": rep.cg_iters,
                   "Z11": [Z[0, 0].real, Z[0, 0].imag], "Z21": [Z[0, 1].real, Z[0, 1].imag]},
+        "plain_fp64": ({"s_per_solve": round(runs["fp64"]["sec"], 4), "iters": runs["fp64"]["rep"].iters,
+                        "converged": runs["fp64"]["rep"].converged, "relres": runs["fp64"]["rep"].relres,
+                        "speedup_of_headline": round(runs["fp64"]["sec"] / sec_per_solve, 3),
+                        "Z11": [runs["fp64"]["Z"][0, 0].real, runs["fp64"]["Z"][0, 0].imag],
+                        "kernels": runs["fp64"]["kernels"]} if "fp64" in runs and head != "fp64" else None),
         "host_setup_s": round(host_setup, 2),
         "kernels": kernels,
         "roofline": roof,

@@ -69,6 +69,10 @@ typedef struct {
   double tol;          /* stop when ||D^-1/2 (b - M x)|| <= tol ||D^-1/2 b||      */
   int32_t restart;     /* GMRES restart length m, 1..64                            */
   int32_t max_iter;    /* total Arnoldi steps                                      */
+  int32_t precision;   /* 0: FP64 throughout.  1: mixed -- each cycle's Krylov     */
+                       /* process (SpMV, block-Jacobi apply, CGS2, basis) runs in  */
+                       /* complex64; cycle residual, Hessenberg least squares,     */
+                       /* solution update and final residual stay FP64            */
 } eddy_solve_opts;
 
 typedef struct {
@@ -83,6 +87,8 @@ typedef struct {
                               /* penalty-free operator + Coulomb projection        */
   int32_t cg_iters;    /* CG steps of the projection's nodal Poisson solve         */
   double div_residual; /* ||G^T b_A|| / ||b||: discrete divergence of the source   */
+  int32_t precision_used;  /* 1 if the complex64 inner loop ran (mixed mode needs */
+                           /* the penalty-free operator; else FP64 is used)        */
 } eddy_solve_report;
 
 /* ---- mesh (host) -------------------------------------------------------

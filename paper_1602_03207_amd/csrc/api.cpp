@@ -65,6 +65,7 @@ struct eddy_op {
   int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
   // numeric
   double2 *val, *ebuf, *minv;
+  float2 *val32, *minv32;       // complex64 copies for the mixed-precision inner loop
   double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *lumped, *s, *nu_reg, *sig_reg;
   double2 *tmp1, *tmp2, *tvec, *red;
   double* rred;
@@ -121,6 +122,8 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->val = c.take<double2>(m->nnz());
   o->ebuf = c.take<double2>(21 * m->nt + 34 * m->nct);
   o->minv = c.take<double2>(nb * kMaxBlock * kMaxBlock);
+  o->val32 = c.take<float2>(m->nnz());
+  o->minv32 = c.take<float2>(nb * kMaxBlock * kMaxBlock);
   o->wval = c.take<double>(m->nnzw());
   o->wtval = c.take<double>(m->nnzw());
   o->wbuf = c.take<double>(24 * m->nt);
@@ -346,6 +349,8 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   launch_permute_r(o->nnzw, o->wtperm, o->wval, o->wtval, s);
   launch_block_invert(o->nb, o->blk_ptr, o->blk_dofs, o->blk_of, o->loc_of, o->rowptr, o->col, o->val, o->ne,
                       o->wrowptr, o->wcol, o->wval, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, o->minv, o->status, s);
+  launch_to_c64(o->nnz, o->val, o->val32, s);
+  launch_to_c64(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv32, s);
   HIP_TRY(hipGetLastError());
   int stat = 0;
   HIP_TRY(hipMemcpyAsync(&stat, o->status, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -414,13 +419,18 @@ eddy_status eddy_export(const eddy_op* o, int32_t* rowptr, int32_t* col, eddy_c1
 namespace {
 struct SolveWs {
   double2 *V, *w, *z, *xt, *bt, *hd, *h1, *h2, *yd, *part;
+  float2 *V32, *w32, *z32;   // complex64 inner loop (precision = 1)
   double *rpart, *nrm;
   // Coulomb projection (nodal CG)
   double2 *psi, *cr, *cz, *cp, *cq, *cg, *cs;
   double* cdiag;
 };
-size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne) {
+size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne, int precision) {
   Carve c(base);
+  const bool mixed = precision == 1;
+  w->V32 = c.take<float2>(mixed ? (int64_t)(m + 1) * n : 0);
+  w->w32 = c.take<float2>(mixed ? n : 0);
+  w->z32 = c.take<float2>(mixed ? n : 0);
   w->psi = c.take<double2>(nv);
   w->cr = c.take<double2>(nv);
   w->cz = c.take<double2>(nv);
@@ -429,7 +439,7 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->cg = c.take<double2>(ne);
   w->cs = c.take<double2>(8);
   w->cdiag = c.take<double>(nv);
-  w->V = c.take<double2>((int64_t)(m + 1) * n);
+  w->V = c.take<double2>(mixed ? 0 : (int64_t)(m + 1) * n);
   w->w = c.take<double2>(n);
   w->z = c.take<double2>(n);
   w->xt = c.take<double2>(n);
@@ -448,16 +458,147 @@ eddy_status check_opts(const eddy_solve_opts* p) {
   if (p->restart < 1 || p->restart > kMaxRestart) { set_error("restart must be in 1..64"); return EDDY_ERR_ARG; }
   if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return EDDY_ERR_ARG; }
   if (!(p->tol > 0)) { set_error("tol must be > 0"); return EDDY_ERR_ARG; }
+  if (p->precision != 0 && p->precision != 1) { set_error("precision must be 0 (fp64) or 1 (mixed)"); return EDDY_ERR_ARG; }
   return EDDY_OK;
 }
 }  // namespace
+
+}  // extern "C"
+
+template <class T>
+struct Inner {
+  T* V;
+  T* w;
+  T* z;
+  const T* val;
+  const T* minv;
+};
+
+// Restarted right-preconditioned GMRES(m) with CGS2.  x~ (W.xt) starts at
+// zero, b~ = W.bt with ||b~|| = bnorm.  Returns with W.xt updated.
+template <class T>
+eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts* opts, bool gauge_op,
+                      double bnorm, int& it, eddy_solve_report& R, hipStream_t s) {
+  using cd = std::complex<double>;
+  const int m = opts->restart;
+  const int64_t n = o->n;
+  double hbuf[8];
+  eddy_status st;
+  auto read_norm = [&](double* out) -> eddy_status {
+    HIP_TRY(hipMemcpyAsync(hbuf, W.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = hbuf[0];
+    return EDDY_OK;
+  };
+  std::vector<cd> H((m + 1) * m), g(m + 1), sn(m), y(m);
+  std::vector<double> cs(m);
+  std::vector<double2> hh1(m + 2), hh2(m + 2);
+  double beta = bnorm;
+  const double2* r = W.bt;     // r0 = b~ (x0 = 0), FP64
+  while (true) {
+    launch_scale_host(n, r, 1.0 / beta, I.V, s);
+    std::fill(g.begin(), g.end(), cd(0));
+    g[0] = beta;
+    int k = 0;
+    bool stop = false;
+    for (int j = 0; j < m; ++j) {
+      T* vj = I.V + (int64_t)j * n;
+      if (o->profile) (void)hipEventRecord(o->ev[0], s);
+      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, vj, I.z, s);
+      if (o->profile) (void)hipEventRecord(o->ev[1], s);
+      if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, (const double2*)I.z, o->tvec, s);
+      if (o->profile) (void)hipEventRecord(o->ev[2], s);
+      launch_spmv(o->n, o->ne, o->rowptr, o->col, I.val, gauge_op ? o->wrowptr : nullptr, o->wcol, o->wval, o->tvec,
+                  (const T*)I.z, nullptr, I.w, s);
+      if (o->profile) (void)hipEventRecord(o->ev[3], s);
+      // CGS2 (Hessenberg entries accumulated in FP64)
+      launch_mdot(n, (const T*)I.V, n, j + 1, (const T*)I.w, W.part, s);
+      launch_reduce_cols(j + 1, W.part, W.h1, s);
+      launch_update(n, (const T*)I.V, n, j + 1, W.h1, I.w, s);
+      launch_mdot(n, (const T*)I.V, n, j + 1, (const T*)I.w, W.part, s);
+      launch_reduce_cols(j + 1, W.part, W.h2, s);
+      launch_update(n, (const T*)I.V, n, j + 1, W.h2, I.w, s);
+      launch_norm2(n, (const T*)I.w, W.rpart, W.nrm, s);
+      launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * n, s);
+      if (o->profile) (void)hipEventRecord(o->ev[4], s);
+      HIP_TRY(hipMemcpyAsync(hh1.data(), W.h1, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(hh2.data(), W.h2, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(hbuf, W.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (o->profile) {
+        for (int c = 0; c < 4; ++c) {
+          float ms = 0;
+          if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, o->ev[c], o->ev[c + 1]) == hipSuccess) {
+            o->prof_ms[c] += ms;
+            o->prof_n[c] += 1;
+          }
+        }
+      }
+      const double hn = hbuf[0];
+      for (int i = 0; i <= j; ++i) H[i * m + j] = cd(hh1[i].x + hh2[i].x, hh1[i].y + hh2[i].y);
+      H[(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        cd a = H[i * m + j], bb = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * bb;
+        H[(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bb;
+      }
+      cd a = H[j * m + j];
+      const double bb = hn;
+      double c;
+      cd sv, rr;
+      if (bb == 0.0) { c = 1.0; sv = 0.0; rr = a; }
+      else if (std::abs(a) == 0.0) { c = 0.0; sv = 1.0; rr = bb; }
+      else {
+        const double t = std::hypot(std::abs(a), bb);
+        c = std::abs(a) / t;
+        sv = (a / std::abs(a)) * bb / t;
+        rr = (a / std::abs(a)) * t;
+      }
+      cs[j] = c;
+      sn[j] = sv;
+      H[j * m + j] = rr;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -std::conj(sv) * g[j];
+      g[j] = c * g[j];
+      ++it;
+      k = j + 1;
+      R.est_relres = std::abs(g[j + 1]) / bnorm;
+      if (!std::isfinite(R.est_relres)) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
+      if (hn == 0.0) R.breakdown = 1;
+      if (R.est_relres <= opts->tol || it >= opts->max_iter || hn == 0.0) { stop = true; break; }
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      cd acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= H[i * m + l] * y[l];
+      y[i] = acc / H[i * m + i];
+    }
+    std::vector<double2> yv(k);
+    for (int i = 0; i < k; ++i) yv[i] = make_double2(y[i].real(), y[i].imag());
+    HIP_TRY(hipMemcpyAsync(W.yd, yv.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
+    launch_combine(n, (const T*)I.V, n, k, W.yd, I.w, s);
+    launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, (const T*)I.w, I.z, s);
+    launch_axpy(n, (const T*)I.z, W.xt, s);
+    // FP64 true residual of the iterated operator: r = b~ - M~ x~
+    op_spmv(o, W.xt, W.bt, W.w, o->tvec, s, gauge_op);
+    launch_norm2(n, (const double2*)W.w, W.rpart, W.nrm, s);
+    if ((st = read_norm(&beta)) != EDDY_OK) return st;
+    R.restarts++;
+    R.relres = beta / bnorm;
+    if (R.relres <= opts->tol || it >= opts->max_iter) break;
+    if (stop && R.breakdown) break;
+    r = W.w;
+  }
+  return EDDY_OK;
+}
+
+extern "C" {
 
 eddy_status eddy_solve_workspace_bytes(const eddy_op* o, const eddy_solve_opts* opts, size_t* bytes) {
   if (!o || !bytes) { set_error("NULL argument"); return EDDY_ERR_ARG; }
   eddy_status st = check_opts(opts);
   if (st != EDDY_OK) return st;
   SolveWs w;
-  *bytes = carve_solve(&w, nullptr, o->n, opts->restart, o->nv, o->ne);
+  *bytes = carve_solve(&w, nullptr, o->n, opts->restart, o->nv, o->ne, opts->precision);
   return EDDY_OK;
 }
 
@@ -471,12 +612,12 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   const int m = opts->restart;
   const int64_t n = o->n;
   SolveWs W;
-  const size_t need = carve_solve(&W, nullptr, n, m, o->nv, o->ne);
+  const size_t need = carve_solve(&W, nullptr, n, m, o->nv, o->ne, opts->precision);
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) {
     set_error("solve workspace too small or misaligned: need " + std::to_string(need) + " bytes");
     return EDDY_ERR_WORKSPACE;
   }
-  carve_solve(&W, ws, n, m, o->nv, o->ne);
+  carve_solve(&W, ws, n, m, o->nv, o->ne, opts->precision);
   hipStream_t s = (hipStream_t)stream;
   using cd = std::complex<double>;
   double hbuf[8];
@@ -512,108 +653,22 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   launch_norm2(n, W.bt, W.rpart, W.nrm, s);
   double bnorm = 0;
   if ((st = read_norm(&bnorm)) != EDDY_OK) return st;
-  double beta = bnorm;
   int it = 0;
-  std::vector<cd> H((m + 1) * m), g(m + 1), sn(m), y(m);
-  std::vector<double> cs(m);
-  std::vector<double2> hh1(m + 2), hh2(m + 2);
+  double beta = 0;
+  // FP64 outer loop: the cycle residual r = b~ - M~ x~, the Hessenberg least
+  // squares and the update of x~ are FP64; the Krylov process of each cycle
+  // (SpMV, block-Jacobi apply, CGS2, basis) runs in the inner storage type.
+  const bool mixed = opts->precision == 1 && !gauge_op;
+  R.precision_used = mixed ? 1 : 0;
   if (bnorm > 0) {
-    // r0 = b~ (x0 = 0)
-    const double2* r = W.bt;
-    while (true) {
-      launch_scale_host(n, r, 1.0 / beta, W.V, s);
-      std::fill(g.begin(), g.end(), cd(0));
-      g[0] = beta;
-      int k = 0;
-      bool stop = false;
-      for (int j = 0; j < m; ++j) {
-        double2* vj = W.V + (int64_t)j * n;
-        if (o->profile) (void)hipEventRecord(o->ev[0], s);
-        launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, vj, W.z, s);
-        if (o->profile) (void)hipEventRecord(o->ev[1], s);
-        if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, W.z, o->tvec, s);
-        if (o->profile) (void)hipEventRecord(o->ev[2], s);
-        launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, gauge_op ? o->wrowptr : nullptr, o->wcol, o->wval,
-                    o->tvec, W.z, nullptr, W.w, s);
-        if (o->profile) (void)hipEventRecord(o->ev[3], s);
-        // CGS2
-        launch_mdot(n, W.V, n, j + 1, W.w, W.part, s);
-        launch_reduce_cols(j + 1, W.part, W.h1, s);
-        launch_update(n, W.V, n, j + 1, W.h1, W.w, s);
-        launch_mdot(n, W.V, n, j + 1, W.w, W.part, s);
-        launch_reduce_cols(j + 1, W.part, W.h2, s);
-        launch_update(n, W.V, n, j + 1, W.h2, W.w, s);
-        launch_norm2(n, W.w, W.rpart, W.nrm, s);
-        launch_scale_by_inv(n, W.w, W.nrm, W.V + (int64_t)(j + 1) * n, s);
-        if (o->profile) (void)hipEventRecord(o->ev[4], s);
-        HIP_TRY(hipMemcpyAsync(hh1.data(), W.h1, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(hh2.data(), W.h2, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(hbuf, W.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (o->profile) {
-          for (int c = 0; c < 4; ++c) {
-            float ms = 0;
-            if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, o->ev[c], o->ev[c + 1]) == hipSuccess) {
-              o->prof_ms[c] += ms;
-              o->prof_n[c] += 1;
-            }
-          }
-        }
-        const double hn = hbuf[0];
-        for (int i = 0; i <= j; ++i) H[i * m + j] = cd(hh1[i].x + hh2[i].x, hh1[i].y + hh2[i].y);
-        H[(j + 1) * m + j] = hn;
-        for (int i = 0; i < j; ++i) {
-          cd a = H[i * m + j], bb = H[(i + 1) * m + j];
-          H[i * m + j] = cs[i] * a + sn[i] * bb;
-          H[(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bb;
-        }
-        cd a = H[j * m + j];
-        const double bb = hn;
-        double c;
-        cd sv, rr;
-        if (bb == 0.0) { c = 1.0; sv = 0.0; rr = a; }
-        else if (std::abs(a) == 0.0) { c = 0.0; sv = 1.0; rr = bb; }
-        else {
-          const double t = std::hypot(std::abs(a), bb);
-          c = std::abs(a) / t;
-          sv = (a / std::abs(a)) * bb / t;
-          rr = (a / std::abs(a)) * t;
-        }
-        cs[j] = c;
-        sn[j] = sv;
-        H[j * m + j] = rr;
-        H[(j + 1) * m + j] = 0.0;
-        g[j + 1] = -std::conj(sv) * g[j];
-        g[j] = c * g[j];
-        ++it;
-        k = j + 1;
-        R.est_relres = std::abs(g[j + 1]) / bnorm;
-        if (!std::isfinite(R.est_relres)) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
-        if (hn == 0.0) R.breakdown = 1;
-        if (R.est_relres <= opts->tol || it >= opts->max_iter || hn == 0.0) { stop = true; break; }
-      }
-      for (int i = k - 1; i >= 0; --i) {
-        cd acc = g[i];
-        for (int l = i + 1; l < k; ++l) acc -= H[i * m + l] * y[l];
-        y[i] = acc / H[i * m + i];
-      }
-      std::vector<double2> yv(k);
-      for (int i = 0; i < k; ++i) yv[i] = make_double2(y[i].real(), y[i].imag());
-      HIP_TRY(hipMemcpyAsync(W.yd, yv.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
-      launch_combine(n, W.V, n, k, W.yd, W.w, s);
-      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, W.w, W.z, s);
-      launch_axpy(n, W.z, W.xt, s);
-      // true residual r = b~ - M~ x~ of the iterated operator
-      op_spmv(o, W.xt, W.bt, W.w, o->tvec, s, gauge_op);
-      launch_norm2(n, W.w, W.rpart, W.nrm, s);
-      if ((st = read_norm(&beta)) != EDDY_OK) return st;
-      HIP_TRY(hipStreamSynchronize(s));   // yv must outlive its copy
-      R.restarts++;
-      R.relres = beta / bnorm;
-      if (R.relres <= opts->tol || it >= opts->max_iter) break;
-      if (stop && R.breakdown) break;
-      r = W.w;
+    if (mixed) {
+      Inner<float2> I{W.V32, W.w32, W.z32, o->val32, o->minv32};
+      st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
+    } else {
+      Inner<double2> I{W.V, W.w, W.z, o->val, o->minv};
+      st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
     }
+    if (st != EDDY_OK) return st;
   } else {
     R.relres = 0;
   }

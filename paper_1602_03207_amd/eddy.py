@@ -26,14 +26,14 @@ class _Params(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int32)]
 
 
 class _Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("relres", C.c_double), ("est_relres", C.c_double),
                 ("seconds", C.c_double), ("gauge_in_operator", C.c_int32), ("cg_iters", C.c_int32),
-                ("div_residual", C.c_double)]
+                ("div_residual", C.c_double), ("precision_used", C.c_int32)]
 
 
 EXPORTS = [
@@ -173,6 +173,7 @@ class SolveReport:
     gauge_in_operator: bool = False
     cg_iters: int = 0
     div_residual: float = 0.0
+    precision_used: int = 0
 
 
 def _aligned(nbytes: int, device):
@@ -226,9 +227,9 @@ class Operator:
         _check(_lib.eddy_rhs_from_current(self._h, _dev(J), _dev(b), _stream()), "eddy_rhs_from_current")
         return b
 
-    def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None):
-        import torch
-        opts = _Opts(tol, restart, max_iter)
+    def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64"):
+        """precision: "fp64", or "mixed" (complex64 Krylov process, FP64 outer residual)."""
+        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1}[precision])
         nbytes = C.c_size_t()
         _check(_lib.eddy_solve_workspace_bytes(self._h, C.byref(opts), C.byref(nbytes)), "eddy_solve_workspace_bytes")
         if self._solve_ws is None or self._solve_ws[2] < nbytes.value:
@@ -240,7 +241,7 @@ class Operator:
                                     C.byref(rep), _stream()), "eddy_solve")
         return x, SolveReport(rep.iters, rep.restarts, bool(rep.converged), bool(rep.breakdown), rep.relres,
                               rep.est_relres, rep.seconds, bool(rep.gauge_in_operator), rep.cg_iters,
-                              rep.div_residual)
+                              rep.div_residual, rep.precision_used)
 
     def spmv(self, x, out=None):
         y = self._c128() if out is None else out

@@ -228,3 +228,20 @@ def test_gauge_modes_and_coulomb_projection():
     assert rep2.gauge_in_operator and rep2.div_residual > 1e-6 and rep2.converged
     xo = remove_v_mean(s, direct(s, s.rhs(Jr)))
     assert np.linalg.norm(x2.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_mixed_precision_c1_matches_oracle():
+    """complex64 Krylov process inside the FP64 outer residual: converges to
+    the FP64 tolerance on the true residual and matches the direct oracle."""
+    from oracle.solve import direct
+    from oracle.post import remove_v_mean
+    m, s, op, J = case("c1")
+    b = op.rhs_from_current(torch.from_numpy(J).cuda())
+    x, rep = op.solve(b, tol=1e-11, precision="mixed")
+    assert rep.converged and rep.precision_used == 1 and rep.relres <= 1e-11
+    xo = remove_v_mean(s, direct(s, s.rhs(J)))
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    assert err <= 1e-9, err
+    x64, rep64 = op.solve(b, tol=1e-11)
+    # the complex64 inner loop costs a few extra cycles at most
+    assert rep.iters <= 2 * rep64.iters + 60
