@@ -21,6 +21,8 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 namespace {
 
+constexpr int kCheckEvery = 8;   // GMRES iterations between host convergence checks
+
 #define HIP_TRY(expr)                                                            \
   do {                                                                           \
     hipError_t e_ = (expr);                                                      \
@@ -73,7 +75,7 @@ struct eddy_op {
   size_t bytes;
   // optional per-kernel-class timing of the GMRES loop (HIP events on the caller's stream)
   bool profile = false;
-  hipEvent_t ev[10] = {};
+  hipEvent_t ev[5 * kCheckEvery] = {};   // per-iteration event ring of one check window
   double prof_ms[5] = {0, 0, 0, 0, 0};
   int64_t prof_n[5] = {0, 0, 0, 0, 0};
   ~eddy_op() {
@@ -424,6 +426,9 @@ struct SolveWs {
   // Coulomb projection (nodal CG)
   double2 *psi, *cr, *cz, *cp, *cq, *cg, *cs;
   double* cdiag;
+  // device Hessenberg least squares
+  double2 *Hd, *snd, *gd;
+  double *csd, *est;
 };
 size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne, int precision) {
   Carve c(base);
@@ -439,6 +444,11 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->cg = c.take<double2>(ne);
   w->cs = c.take<double2>(8);
   w->cdiag = c.take<double>(nv);
+  w->Hd = c.take<double2>((int64_t)(m + 1) * m);
+  w->snd = c.take<double2>(m + 1);
+  w->gd = c.take<double2>(m + 2);
+  w->csd = c.take<double>(m + 1);
+  w->est = c.take<double>(m + 1);
   w->V = c.take<double2>(mixed ? 0 : (int64_t)(m + 1) * n);
   w->w = c.take<double2>(n);
   w->z = c.take<double2>(n);
@@ -465,6 +475,8 @@ eddy_status check_opts(const eddy_solve_opts* p) {
 
 }  // extern "C"
 
+namespace {
+
 template <class T>
 struct Inner {
   T* V;
@@ -479,9 +491,9 @@ struct Inner {
 template <class T>
 eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts* opts, bool gauge_op,
                       double bnorm, int& it, eddy_solve_report& R, hipStream_t s) {
-  using cd = std::complex<double>;
   const int m = opts->restart;
   const int64_t n = o->n;
+  const bool fused = m <= kFusedQ;
   double hbuf[8];
   eddy_status st;
   auto read_norm = [&](double* out) -> eddy_status {
@@ -490,91 +502,80 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
     *out = hbuf[0];
     return EDDY_OK;
   };
-  std::vector<cd> H((m + 1) * m), g(m + 1), sn(m), y(m);
-  std::vector<double> cs(m);
-  std::vector<double2> hh1(m + 2), hh2(m + 2);
+  std::vector<double> est(m + 1);
   double beta = bnorm;
   const double2* r = W.bt;     // r0 = b~ (x0 = 0), FP64
   while (true) {
     launch_scale_host(n, r, 1.0 / beta, I.V, s);
-    std::fill(g.begin(), g.end(), cd(0));
-    g[0] = beta;
-    int k = 0;
+    int k = 0, jstart = 0;
     bool stop = false;
     for (int j = 0; j < m; ++j) {
       T* vj = I.V + (int64_t)j * n;
-      if (o->profile) (void)hipEventRecord(o->ev[0], s);
+      hipEvent_t* ev = o->ev + 5 * (j - jstart);
+      if (o->profile) (void)hipEventRecord(ev[0], s);
       launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, vj, I.z, s);
-      if (o->profile) (void)hipEventRecord(o->ev[1], s);
+      if (o->profile) (void)hipEventRecord(ev[1], s);
       if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, (const double2*)I.z, o->tvec, s);
-      if (o->profile) (void)hipEventRecord(o->ev[2], s);
+      if (o->profile) (void)hipEventRecord(ev[2], s);
       launch_spmv(o->n, o->ne, o->rowptr, o->col, I.val, gauge_op ? o->wrowptr : nullptr, o->wcol, o->wval, o->tvec,
                   (const T*)I.z, nullptr, I.w, s);
-      if (o->profile) (void)hipEventRecord(o->ev[3], s);
-      // CGS2 (Hessenberg entries accumulated in FP64)
-      launch_mdot(n, (const T*)I.V, n, j + 1, (const T*)I.w, W.part, s);
-      launch_reduce_cols(j + 1, W.part, W.h1, s);
-      launch_update(n, (const T*)I.V, n, j + 1, W.h1, I.w, s);
-      launch_mdot(n, (const T*)I.V, n, j + 1, (const T*)I.w, W.part, s);
-      launch_reduce_cols(j + 1, W.part, W.h2, s);
-      launch_update(n, (const T*)I.V, n, j + 1, W.h2, I.w, s);
-      launch_norm2(n, (const T*)I.w, W.rpart, W.nrm, s);
+      if (o->profile) (void)hipEventRecord(ev[3], s);
+      // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, ||w|| (FP64 accumulation)
+      const int q = j + 1;
+      if (fused) {
+        launch_mdot_q(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
+        launch_reduce_cols(q, W.part, W.h1, s);
+        launch_update_mdot_q(n, (const T*)I.V, n, q, W.h1, I.w, W.part, s);
+        launch_reduce_cols(q, W.part, W.h2, s);
+        launch_update_norm_q(n, (const T*)I.V, n, q, W.h2, I.w, W.rpart, W.nrm, s);
+      } else {
+        launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
+        launch_reduce_cols(q, W.part, W.h1, s);
+        launch_update(n, (const T*)I.V, n, q, W.h1, I.w, s);
+        launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
+        launch_reduce_cols(q, W.part, W.h2, s);
+        launch_update(n, (const T*)I.V, n, q, W.h2, I.w, s);
+        launch_norm2(n, (const T*)I.w, W.rpart, W.nrm, s);
+      }
       launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * n, s);
-      if (o->profile) (void)hipEventRecord(o->ev[4], s);
-      HIP_TRY(hipMemcpyAsync(hh1.data(), W.h1, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(hh2.data(), W.h2, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(hbuf, W.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      if (o->profile) (void)hipEventRecord(ev[4], s);
+      launch_givens(j, m, W.h1, W.h2, W.nrm, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est, s);
+      ++it;
+      const bool check = (j + 1 - jstart) == kCheckEvery || j == m - 1 || it >= opts->max_iter;
+      if (!check) continue;
+      HIP_TRY(hipMemcpyAsync(est.data() + jstart, W.est + jstart, sizeof(double) * (j + 1 - jstart),
+                             hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       if (o->profile) {
-        for (int c = 0; c < 4; ++c) {
-          float ms = 0;
-          if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, o->ev[c], o->ev[c + 1]) == hipSuccess) {
-            o->prof_ms[c] += ms;
-            o->prof_n[c] += 1;
+        for (int jj = 0; jj <= j - jstart; ++jj)
+          for (int c = 0; c < 4; ++c) {
+            float ms = 0;
+            if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, o->ev[5 * jj + c], o->ev[5 * jj + c + 1]) == hipSuccess) {
+              o->prof_ms[c] += ms;
+              o->prof_n[c] += 1;
+            }
           }
+      }
+      for (int jj = jstart; jj <= j; ++jj) {
+        if (!std::isfinite(est[jj])) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
+        if (est[jj] <= opts->tol) {
+          if (est[jj] == 0.0) R.breakdown = 1;
+          it -= j - jj;       // steps after jj were computed but are not used
+          k = jj + 1;
+          stop = true;
+          break;
         }
       }
-      const double hn = hbuf[0];
-      for (int i = 0; i <= j; ++i) H[i * m + j] = cd(hh1[i].x + hh2[i].x, hh1[i].y + hh2[i].y);
-      H[(j + 1) * m + j] = hn;
-      for (int i = 0; i < j; ++i) {
-        cd a = H[i * m + j], bb = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * bb;
-        H[(i + 1) * m + j] = -std::conj(sn[i]) * a + cs[i] * bb;
+      if (!stop && it >= opts->max_iter) {
+        k = j + 1;
+        stop = true;
       }
-      cd a = H[j * m + j];
-      const double bb = hn;
-      double c;
-      cd sv, rr;
-      if (bb == 0.0) { c = 1.0; sv = 0.0; rr = a; }
-      else if (std::abs(a) == 0.0) { c = 0.0; sv = 1.0; rr = bb; }
-      else {
-        const double t = std::hypot(std::abs(a), bb);
-        c = std::abs(a) / t;
-        sv = (a / std::abs(a)) * bb / t;
-        rr = (a / std::abs(a)) * t;
-      }
-      cs[j] = c;
-      sn[j] = sv;
-      H[j * m + j] = rr;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -std::conj(sv) * g[j];
-      g[j] = c * g[j];
-      ++it;
-      k = j + 1;
-      R.est_relres = std::abs(g[j + 1]) / bnorm;
-      if (!std::isfinite(R.est_relres)) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
-      if (hn == 0.0) R.breakdown = 1;
-      if (R.est_relres <= opts->tol || it >= opts->max_iter || hn == 0.0) { stop = true; break; }
+      if (stop) break;
+      jstart = j + 1;
     }
-    for (int i = k - 1; i >= 0; --i) {
-      cd acc = g[i];
-      for (int l = i + 1; l < k; ++l) acc -= H[i * m + l] * y[l];
-      y[i] = acc / H[i * m + i];
-    }
-    std::vector<double2> yv(k);
-    for (int i = 0; i < k; ++i) yv[i] = make_double2(y[i].real(), y[i].imag());
-    HIP_TRY(hipMemcpyAsync(W.yd, yv.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
+    if (!stop) k = m;
+    R.est_relres = est[k - 1];
+    launch_backsolve(k, m, W.Hd, W.gd, W.yd, s);
     launch_combine(n, (const T*)I.V, n, k, W.yd, I.w, s);
     launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, (const T*)I.w, I.z, s);
     launch_axpy(n, (const T*)I.z, W.xt, s);
@@ -590,6 +591,8 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
   }
   return EDDY_OK;
 }
+
+}  // namespace
 
 extern "C" {
 

@@ -61,6 +61,20 @@ void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y,
 template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st);
 void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
+// fused CGS2 passes for q <= kFusedQ vectors
+constexpr int kFusedQ = 32;
+template <class T>
+void launch_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st);
+template <class T>
+void launch_update_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double2* partial,
+                          hipStream_t st);
+template <class T>
+void launch_update_norm_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
+                          double* out_norm, hipStream_t st);
+// Hessenberg least squares on the device
+void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
+                   double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);
+void launch_backsolve(int k, int m, const double2* H, const double2* g, double2* y, hipStream_t st);
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st);
 void launch_zero(int64_t n, double2* x, hipStream_t st);
 void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, double2* V, double2* scratch,

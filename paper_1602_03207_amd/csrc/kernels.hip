@@ -716,6 +716,172 @@ __global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restric
   if (i < n) x[i] = cadd(x[i], ld2(z[i]));
 }
 
+// ---- fused CGS2 passes (q <= Q vectors; FP64 accumulation) ----
+// Sum one value over the 64 lanes of a wavefront (fixed butterfly).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Block partial of q complex accumulators -> partial[k * kRedBlocks + blockIdx.x]
+template <int Q>
+__device__ __forceinline__ void block_partials(const double2 (&acc)[Q], int q, double2 (*red)[Q],
+                                               double2* __restrict__ partial) {
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (k < q) {
+      const double re = wave_sum(acc[k].x), im = wave_sum(acc[k].y);
+      if (ln == 0) red[wv][k] = make_double2(re, im);
+    }
+  __syncthreads();
+  if (threadIdx.x < q) {
+    const int k = threadIdx.x;
+    partial[(int64_t)k * kRedBlocks + blockIdx.x] =
+        make_double2((red[0][k].x + red[1][k].x) + (red[2][k].x + red[3][k].x),
+                     (red[0][k].y + red[1][k].y) + (red[2][k].y + red[3][k].y));
+  }
+}
+
+// partial = V^H w over q vectors, w read once
+template <class T, int Q>
+__global__ __launch_bounds__(kThreads) void k_mdot_q(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                     const T* __restrict__ w, double2* __restrict__ partial) {
+  __shared__ double2 red[4][Q];
+  double2 acc[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 wi = ld2(w[i]);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (k < q) acc[k] = cfma_conj(ld2(V[(int64_t)k * ldv + i]), wi, acc[k]);
+  }
+  block_partials<Q>(acc, q, red, partial);
+}
+
+// w <- w - V h, then partial = V^H w (the updated, stored w)
+template <class T, int Q>
+__global__ __launch_bounds__(kThreads) void k_update_mdot_q(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                            const double2* __restrict__ h, T* __restrict__ w,
+                                                            double2* __restrict__ partial) {
+  __shared__ double2 red[4][Q];
+  __shared__ double2 hs[Q];
+  if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  double2 acc[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 wi = ld2(w[i]);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (k < q) {
+        const double2 v = ld2(V[(int64_t)k * ldv + i]);
+        const double2 hk = hs[k];
+        wi.x -= v.x * hk.x - v.y * hk.y;
+        wi.y -= v.x * hk.y + v.y * hk.x;
+      }
+    const T ws = st2<T>(wi);
+    w[i] = ws;
+    wi = ld2(ws);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (k < q) acc[k] = cfma_conj(ld2(V[(int64_t)k * ldv + i]), wi, acc[k]);
+  }
+  block_partials<Q>(acc, q, red, partial);
+}
+
+// w <- w - V h, rpart = ||w||^2 partial per block
+template <class T, int Q>
+__global__ __launch_bounds__(kThreads) void k_update_norm_q(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                            const double2* __restrict__ h, T* __restrict__ w,
+                                                            double* __restrict__ rpart) {
+  __shared__ double2 hs[Q];
+  __shared__ double sh[4];
+  if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 wi = ld2(w[i]);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (k < q) {
+        const double2 v = ld2(V[(int64_t)k * ldv + i]);
+        const double2 hk = hs[k];
+        wi.x -= v.x * hk.x - v.y * hk.y;
+        wi.y -= v.x * hk.y + v.y * hk.x;
+      }
+    const T ws = st2<T>(wi);
+    w[i] = ws;
+    wi = ld2(ws);
+    acc = fma(wi.x, wi.x, fma(wi.y, wi.y, acc));
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) rpart[blockIdx.x] = acc;
+}
+
+// ---- Hessenberg least squares on the device (one thread) ----
+// Column j of H (row-major, leading dimension m) = h1 + h2 with H(j+1, j) =
+// ||w||; applies the previous rotations, forms the new one, updates g and
+// writes est[j] = |g(j+1)| / bnorm.  At j = 0, g is reset to (beta, 0, ...).
+__global__ void k_givens(int j, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                         const double* __restrict__ nrm, double2* __restrict__ H, double* __restrict__ cs,
+                         double2* __restrict__ sn, double2* __restrict__ g, double beta, double bnorm,
+                         double* __restrict__ est) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (j == 0) {
+    for (int i = 0; i <= m; ++i) g[i] = make_double2(0.0, 0.0);
+    g[0] = make_double2(beta, 0.0);
+  }
+  for (int i = 0; i <= j; ++i) H[i * m + j] = cadd(h1[i], h2[i]);
+  const double hn = nrm[0];
+  for (int i = 0; i < j; ++i) {
+    const double2 a = H[i * m + j], b = H[(i + 1) * m + j];
+    const double c = cs[i];
+    const double2 s = sn[i];
+    H[i * m + j] = cadd(make_double2(c * a.x, c * a.y), cmul(s, b));
+    const double2 sc = make_double2(s.x, -s.y);
+    H[(i + 1) * m + j] = csub(make_double2(c * b.x, c * b.y), cmul(sc, a));
+  }
+  const double2 a = H[j * m + j];
+  const double aa = sqrt(a.x * a.x + a.y * a.y);
+  double c;
+  double2 s, r;
+  if (hn == 0.0) {
+    c = 1.0; s = make_double2(0.0, 0.0); r = a;
+  } else if (aa == 0.0) {
+    c = 0.0; s = make_double2(1.0, 0.0); r = make_double2(hn, 0.0);
+  } else {
+    const double t = hypot(aa, hn);
+    c = aa / t;
+    const double2 ph = make_double2(a.x / aa, a.y / aa);
+    s = make_double2(ph.x * hn / t, ph.y * hn / t);
+    r = make_double2(ph.x * t, ph.y * t);
+  }
+  cs[j] = c;
+  sn[j] = s;
+  H[j * m + j] = r;
+  const double2 gj = g[j];
+  const double2 sc = make_double2(s.x, -s.y);
+  const double2 ng = cmul(sc, gj);
+  g[j + 1] = make_double2(-ng.x, -ng.y);
+  g[j] = make_double2(c * gj.x, c * gj.y);
+  est[j] = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / bnorm;
+}
+
+// y = H(0:k,0:k)^-1 g(0:k) (upper triangular), one thread
+__global__ void k_backsolve(int k, int m, const double2* __restrict__ H, const double2* __restrict__ g,
+                            double2* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double2 acc = g[i];
+    for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(H[i * m + l], y[l]));
+    const double2 d = H[i * m + i];
+    const double den = d.x * d.x + d.y * d.y;
+    y[i] = cmul(acc, make_double2(d.x / den, -d.y / den));
+  }
+}
+
 // out = (complex64) in
 __global__ __launch_bounds__(kThreads) void k_to_c64(int64_t n, const double2* __restrict__ in,
                                                      float2* __restrict__ out) {
@@ -888,6 +1054,28 @@ template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
   k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x);
 }
+template <class T>
+void launch_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st) {
+  k_mdot_q<T, kFusedQ><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, w, partial);
+}
+template <class T>
+void launch_update_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double2* partial,
+                          hipStream_t st) {
+  k_update_mdot_q<T, kFusedQ><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, partial);
+}
+template <class T>
+void launch_update_norm_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
+                          double* out_norm, hipStream_t st) {
+  k_update_norm_q<T, kFusedQ><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart);
+  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm);
+}
+void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
+                   double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st) {
+  k_givens<<<1, 64, 0, st>>>(j, m, h1, h2, nrm, H, cs, sn, g, beta, bnorm, est);
+}
+void launch_backsolve(int k, int m, const double2* H, const double2* g, double2* y, hipStream_t st) {
+  k_backsolve<<<1, 64, 0, st>>>(k, m, H, g, y);
+}
 void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   k_to_c64<<<blocks_for(n), kThreads, 0, st>>>(n, in, out);
 }
@@ -901,7 +1089,12 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   template void launch_scale_by_inv<T>(int64_t, const T*, const double*, T*, hipStream_t);                        \
   template void launch_scale_host<double2, T>(int64_t, const double2*, double, T*, hipStream_t);                  \
   template void launch_combine<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);              \
-  template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);
+  template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);                                        \
+  template void launch_mdot_q<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t);               \
+  template void launch_update_mdot_q<T>(int64_t, const T*, int64_t, int, const double2*, T*, double2*,            \
+                                        hipStream_t);                                                             \
+  template void launch_update_norm_q<T>(int64_t, const T*, int64_t, int, const double2*, T*, double*, double*,    \
+                                        hipStream_t);
 EDDY_INST(double2)
 EDDY_INST(float2)
 #undef EDDY_INST
