@@ -67,6 +67,7 @@ struct eddy_op {
   int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
   // numeric
   double2 *val, *ebuf, *minv;
+  double* gscr;                 // gauge part of the diagonal blocks (assembly scratch)
   float2 *val32, *minv32;       // complex64 copies for the mixed-precision inner loop
   double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *lumped, *s, *nu_reg, *sig_reg;
   double2 *tmp1, *tmp2, *tvec, *red;
@@ -124,6 +125,7 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->val = c.take<double2>(m->nnz());
   o->ebuf = c.take<double2>(21 * m->nt + 34 * m->nct);
   o->minv = c.take<double2>(nb * kMaxBlock * kMaxBlock);
+  o->gscr = c.take<double>(nb * kMaxBlock * kMaxBlock);
   o->val32 = c.take<float2>(m->nnz());
   o->minv32 = c.take<float2>(nb * kMaxBlock * kMaxBlock);
   o->wval = c.take<double>(m->nnzw());
@@ -350,7 +352,7 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   launch_scale_w(o->ne, o->wrowptr, o->wval, o->s, s);
   launch_permute_r(o->nnzw, o->wtperm, o->wval, o->wtval, s);
   launch_block_invert(o->nb, o->blk_ptr, o->blk_dofs, o->blk_of, o->loc_of, o->rowptr, o->col, o->val, o->ne,
-                      o->wrowptr, o->wcol, o->wval, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, o->minv, o->status, s);
+                      o->wrowptr, o->wcol, o->wval, o->d0tau, o->gscr, o->minv, o->status, s);
   launch_to_c64(o->nnz, o->val, o->val32, s);
   launch_to_c64(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv32, s);
   HIP_TRY(hipGetLastError());
@@ -493,7 +495,6 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
                       double bnorm, int& it, eddy_solve_report& R, hipStream_t s) {
   const int m = opts->restart;
   const int64_t n = o->n;
-  const bool fused = m <= kFusedQ;
   double hbuf[8];
   eddy_status st;
   auto read_norm = [&](double* out) -> eddy_status {
@@ -522,21 +523,12 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       if (o->profile) (void)hipEventRecord(ev[3], s);
       // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, ||w|| (FP64 accumulation)
       const int q = j + 1;
-      if (fused) {
-        launch_mdot_q(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
-        launch_reduce_cols(q, W.part, W.h1, s);
-        launch_update_mdot_q(n, (const T*)I.V, n, q, W.h1, I.w, W.part, s);
-        launch_reduce_cols(q, W.part, W.h2, s);
-        launch_update_norm_q(n, (const T*)I.V, n, q, W.h2, I.w, W.rpart, W.nrm, s);
-      } else {
-        launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
-        launch_reduce_cols(q, W.part, W.h1, s);
-        launch_update(n, (const T*)I.V, n, q, W.h1, I.w, s);
-        launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
-        launch_reduce_cols(q, W.part, W.h2, s);
-        launch_update(n, (const T*)I.V, n, q, W.h2, I.w, s);
-        launch_norm2(n, (const T*)I.w, W.rpart, W.nrm, s);
-      }
+      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
+      launch_reduce_cols(q, W.part, W.h1, s);
+      launch_update(n, (const T*)I.V, n, q, W.h1, I.w, s);
+      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
+      launch_reduce_cols(q, W.part, W.h2, s);
+      launch_update_norm(n, (const T*)I.V, n, q, W.h2, I.w, W.rpart, W.nrm, s);
       launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * n, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
       launch_givens(j, m, W.h1, W.h2, W.nrm, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est, s);

@@ -25,10 +25,11 @@ void launch_equilibrate(int64_t n, int64_t ne, const int* diagpos, const double2
                         hipStream_t st);
 void launch_scale_rows(int64_t n, const int* rowptr, const int* col, double2* val, const double* s, hipStream_t st);
 void launch_scale_w(int64_t ne, const int* wrowptr, double* wval, const double* s, hipStream_t st);
+// block inverses: gauge blocks into gscr (nb * 64 * 64 doubles), then LDS Gauss-Jordan
 void launch_block_invert(int64_t nb, const int* blk_ptr, const int* blk_dofs, const int* blk_of, const int* loc_of,
                          const int* rowptr, const int* col, const double2* val, int64_t ne, const int* wrowptr,
-                         const int* wcol, const double* wval, const int* wtrowptr, const int* wtcol,
-                         const double* wtval, const double* d0tau, double2* minv, int* status, hipStream_t st);
+                         const int* wcol, const double* wval, const double* d0tau, double* gscr, double2* minv,
+                         int* status, hipStream_t st);
 void launch_rhs_elem(int64_t nt, const double* xyz, const int* tet, const uint8_t* signbits, const double* J,
                      double* rbuf, hipStream_t st);
 
@@ -61,16 +62,10 @@ void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y,
 template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st);
 void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
-// fused CGS2 passes for q <= kFusedQ vectors
-constexpr int kFusedQ = 32;
+// second CGS2 update fused with the norm of the new vector
 template <class T>
-void launch_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st);
-template <class T>
-void launch_update_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double2* partial,
-                          hipStream_t st);
-template <class T>
-void launch_update_norm_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
-                          double* out_norm, hipStream_t st);
+void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
+                        double* out_norm, hipStream_t st);
 // Hessenberg least squares on the device
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);

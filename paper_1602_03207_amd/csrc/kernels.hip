@@ -252,37 +252,27 @@ __global__ __launch_bounds__(kThreads) void k_scale_w(int64_t ne, const int* __r
   for (int p = wrowptr[e]; p < wrowptr[e + 1]; ++p) wval[p] *= se;
 }
 
-// ---------------------------------------------------------------------------
-// Dense inverse of one equilibrated diagonal block per 64-thread workgroup:
-// gather the block (CSR part + factored gauge part) into LDS column-major,
-// Gauss-Jordan with partial pivoting (thread i owns row i; thread j owns
-// column j for row swaps), undo the column permutation, store column-major.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMaxBlock) void k_block_invert(
-    const int* __restrict__ blk_ptr, const int* __restrict__ blk_dofs, const int* __restrict__ blk_of,
-    const int* __restrict__ loc_of, const int* __restrict__ rowptr, const int* __restrict__ col,
-    const double2* __restrict__ val, int64_t ne, const int* __restrict__ wrowptr, const int* __restrict__ wcol,
-    const double* __restrict__ wval, const int* __restrict__ wtrowptr, const int* __restrict__ wtcol,
-    const double* __restrict__ wtval, const double* __restrict__ d0tau, double2* __restrict__ minv,
-    int* __restrict__ status) {
-  __shared__ double2 A[kMaxBlock * kMaxBlock];   // A(i, j) at j * 64 + i
-  __shared__ int perm[kMaxBlock];
-  __shared__ int wn[kMaxBlock][kMaxWRow];         // nodes of W~ row i
-  __shared__ double wv[kMaxBlock][kMaxWRow];      // W~_in
-  __shared__ double wd[kMaxBlock][kMaxWRow];      // W~_in tau / D0_n
+// Gauge part of one diagonal block: G(i, j) = sum over shared nodes n of
+// W~_in W~_jn tau / D0_n for the A rows of the block, W~ rows staged in LDS;
+// written column-major to gscr[k * 64 * 64 + j * 64 + i] (rows i < sz).
+__global__ __launch_bounds__(kMaxBlock) void k_block_gauge(const int* __restrict__ blk_ptr,
+                                                           const int* __restrict__ blk_dofs, int64_t ne,
+                                                           const int* __restrict__ wrowptr,
+                                                           const int* __restrict__ wcol,
+                                                           const double* __restrict__ wval,
+                                                           const double* __restrict__ d0tau,
+                                                           double* __restrict__ gscr) {
+  __shared__ int wn[kMaxBlock][kMaxWRow];
+  __shared__ double wv[kMaxBlock][kMaxWRow];
+  __shared__ double wd[kMaxBlock][kMaxWRow];
   __shared__ int wc[kMaxBlock];
   const int k = blockIdx.x;
   const int i = threadIdx.x;
   const int b0 = blk_ptr[k];
   const int sz = blk_ptr[k + 1] - b0;
-  for (int j = 0; j < kMaxBlock; ++j) A[j * kMaxBlock + i] = make_double2(0.0, 0.0);
   int cnt = 0;
   if (i < sz) {
     const int r = blk_dofs[b0 + i];
-    for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
-      const int c = col[p];
-      if (blk_of[c] == k) A[loc_of[c] * kMaxBlock + i] = val[p];
-    }
     if (r < ne) {
       cnt = wrowptr[r + 1] - wrowptr[r];      // <= kMaxWRow, checked on the host
       for (int q = 0; q < cnt; ++q) {
@@ -295,17 +285,51 @@ __global__ __launch_bounds__(kMaxBlock) void k_block_invert(
   }
   wc[i] = cnt;
   __syncthreads();
-  // gauge block tau (W~ D0^-1 W~^T)_ij = sum over shared nodes n of W~_in W~_jn tau / D0_n
-  if (cnt > 0) {
-    for (int j = 0; j < sz; ++j) {
-      const int cj = wc[j];
-      double acc = 0.0;
-      for (int q = 0; q < cnt; ++q) {
-        const int nq = wn[i][q];
-        for (int u = 0; u < cj; ++u)
-          if (wn[j][u] == nq) acc += wd[i][q] * wv[j][u];
+  if (i >= sz) return;
+  double* out = gscr + (int64_t)k * kMaxBlock * kMaxBlock;
+  for (int j = 0; j < sz; ++j) {
+    const int cj = wc[j];
+    double acc = 0.0;
+    for (int q = 0; q < cnt; ++q) {
+      const int nq = wn[i][q];
+      for (int u = 0; u < cj; ++u)
+        if (wn[j][u] == nq) acc += wd[i][q] * wv[j][u];
+    }
+    out[j * kMaxBlock + i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense inverse of one equilibrated diagonal block per 64-thread workgroup:
+// gather the block (CSR part + the gauge part from k_block_gauge) into LDS
+// column-major, Gauss-Jordan with partial pivoting (thread i owns row i;
+// thread j owns column j for row swaps), undo the column permutation, store
+// column-major.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kMaxBlock) void k_block_invert(
+    const int* __restrict__ blk_ptr, const int* __restrict__ blk_dofs, const int* __restrict__ blk_of,
+    const int* __restrict__ loc_of, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const double2* __restrict__ val, const double* __restrict__ gscr, double2* __restrict__ minv,
+    int* __restrict__ status) {
+  __shared__ double2 A[kMaxBlock * kMaxBlock];   // A(i, j) at j * 64 + i
+  __shared__ int perm[kMaxBlock];
+  const int k = blockIdx.x;
+  const int i = threadIdx.x;
+  const int b0 = blk_ptr[k];
+  const int sz = blk_ptr[k + 1] - b0;
+  const double* gk = gscr + (int64_t)k * kMaxBlock * kMaxBlock;
+  for (int j = 0; j < kMaxBlock; ++j)
+    A[j * kMaxBlock + i] = make_double2((i < sz && j < sz) ? gk[j * kMaxBlock + i] : 0.0, 0.0);
+  __syncthreads();
+  if (i < sz) {
+    const int r = blk_dofs[b0 + i];
+    for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+      const int c = col[p];
+      if (blk_of[c] == k) {
+        const double2 v = val[p];
+        A[loc_of[c] * kMaxBlock + i].x += v.x;
+        A[loc_of[c] * kMaxBlock + i].y += v.y;
       }
-      A[j * kMaxBlock + i].x += acc;
     }
   }
   __syncthreads();
@@ -716,101 +740,25 @@ __global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restric
   if (i < n) x[i] = cadd(x[i], ld2(z[i]));
 }
 
-// ---- fused CGS2 passes (q <= Q vectors; FP64 accumulation) ----
-// Sum one value over the 64 lanes of a wavefront (fixed butterfly).
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-// Block partial of q complex accumulators -> partial[k * kRedBlocks + blockIdx.x]
-template <int Q>
-__device__ __forceinline__ void block_partials(const double2 (&acc)[Q], int q, double2 (*red)[Q],
-                                               double2* __restrict__ partial) {
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-#pragma unroll
-  for (int k = 0; k < Q; ++k)
-    if (k < q) {
-      const double re = wave_sum(acc[k].x), im = wave_sum(acc[k].y);
-      if (ln == 0) red[wv][k] = make_double2(re, im);
-    }
-  __syncthreads();
-  if (threadIdx.x < q) {
-    const int k = threadIdx.x;
-    partial[(int64_t)k * kRedBlocks + blockIdx.x] =
-        make_double2((red[0][k].x + red[1][k].x) + (red[2][k].x + red[3][k].x),
-                     (red[0][k].y + red[1][k].y) + (red[2][k].y + red[3][k].y));
-  }
-}
-
-// partial = V^H w over q vectors, w read once
-template <class T, int Q>
-__global__ __launch_bounds__(kThreads) void k_mdot_q(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                     const T* __restrict__ w, double2* __restrict__ partial) {
-  __shared__ double2 red[4][Q];
-  double2 acc[Q];
-#pragma unroll
-  for (int k = 0; k < Q; ++k) acc[k] = make_double2(0.0, 0.0);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 wi = ld2(w[i]);
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      if (k < q) acc[k] = cfma_conj(ld2(V[(int64_t)k * ldv + i]), wi, acc[k]);
-  }
-  block_partials<Q>(acc, q, red, partial);
-}
-
-// w <- w - V h, then partial = V^H w (the updated, stored w)
-template <class T, int Q>
-__global__ __launch_bounds__(kThreads) void k_update_mdot_q(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                            const double2* __restrict__ h, T* __restrict__ w,
-                                                            double2* __restrict__ partial) {
-  __shared__ double2 red[4][Q];
-  __shared__ double2 hs[Q];
-  if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
-  double2 acc[Q];
-#pragma unroll
-  for (int k = 0; k < Q; ++k) acc[k] = make_double2(0.0, 0.0);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double2 wi = ld2(w[i]);
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      if (k < q) {
-        const double2 v = ld2(V[(int64_t)k * ldv + i]);
-        const double2 hk = hs[k];
-        wi.x -= v.x * hk.x - v.y * hk.y;
-        wi.y -= v.x * hk.y + v.y * hk.x;
-      }
-    const T ws = st2<T>(wi);
-    w[i] = ws;
-    wi = ld2(ws);
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      if (k < q) acc[k] = cfma_conj(ld2(V[(int64_t)k * ldv + i]), wi, acc[k]);
-  }
-  block_partials<Q>(acc, q, red, partial);
-}
-
-// w <- w - V h, rpart = ||w||^2 partial per block
-template <class T, int Q>
-__global__ __launch_bounds__(kThreads) void k_update_norm_q(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                            const double2* __restrict__ h, T* __restrict__ w,
-                                                            double* __restrict__ rpart) {
-  __shared__ double2 hs[Q];
+// w <- w - V h (FP64 arithmetic, stored in T) and rpart = per-block ||w||^2:
+// the second CGS2 update fused with the norm of the new basis vector.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_update_norm(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                          const double2* __restrict__ h, T* __restrict__ w,
+                                                          double* __restrict__ rpart) {
+  __shared__ double2 hs[kMaxRestart + 1];
   __shared__ double sh[4];
   if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double2 wi = ld2(w[i]);
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      if (k < q) {
-        const double2 v = ld2(V[(int64_t)k * ldv + i]);
-        const double2 hk = hs[k];
-        wi.x -= v.x * hk.x - v.y * hk.y;
-        wi.y -= v.x * hk.y + v.y * hk.x;
-      }
+    for (int k = 0; k < q; ++k) {
+      const double2 v = ld2(V[(int64_t)k * ldv + i]);
+      const double2 hk = hs[k];
+      wi.x -= v.x * hk.x - v.y * hk.y;
+      wi.y -= v.x * hk.y + v.y * hk.x;
+    }
     const T ws = st2<T>(wi);
     w[i] = ws;
     wi = ld2(ws);
@@ -995,11 +943,11 @@ void launch_scale_w(int64_t ne, const int* wrowptr, double* wval, const double* 
 }
 void launch_block_invert(int64_t nb, const int* blk_ptr, const int* blk_dofs, const int* blk_of, const int* loc_of,
                          const int* rowptr, const int* col, const double2* val, int64_t ne, const int* wrowptr,
-                         const int* wcol, const double* wval, const int* wtrowptr, const int* wtcol,
-                         const double* wtval, const double* d0tau, double2* minv, int* status, hipStream_t st) {
+                         const int* wcol, const double* wval, const double* d0tau, double* gscr, double2* minv,
+                         int* status, hipStream_t st) {
   if (nb <= 0) return;
-  k_block_invert<<<(unsigned)nb, kMaxBlock, 0, st>>>(blk_ptr, blk_dofs, blk_of, loc_of, rowptr, col, val, ne,
-                                                      wrowptr, wcol, wval, wtrowptr, wtcol, wtval, d0tau, minv,
+  k_block_gauge<<<(unsigned)nb, kMaxBlock, 0, st>>>(blk_ptr, blk_dofs, ne, wrowptr, wcol, wval, d0tau, gscr);
+  k_block_invert<<<(unsigned)nb, kMaxBlock, 0, st>>>(blk_ptr, blk_dofs, blk_of, loc_of, rowptr, col, val, gscr, minv,
                                                       status);
 }
 void launch_rhs_elem(int64_t nt, const double* xyz, const int* tet, const uint8_t* signbits, const double* J,
@@ -1055,18 +1003,9 @@ void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
   k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x);
 }
 template <class T>
-void launch_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st) {
-  k_mdot_q<T, kFusedQ><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, w, partial);
-}
-template <class T>
-void launch_update_mdot_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double2* partial,
-                          hipStream_t st) {
-  k_update_mdot_q<T, kFusedQ><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, partial);
-}
-template <class T>
-void launch_update_norm_q(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
-                          double* out_norm, hipStream_t st) {
-  k_update_norm_q<T, kFusedQ><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart);
+void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
+                        double* out_norm, hipStream_t st) {
+  k_update_norm<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart);
   k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm);
 }
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
@@ -1090,11 +1029,8 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   template void launch_scale_host<double2, T>(int64_t, const double2*, double, T*, hipStream_t);                  \
   template void launch_combine<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);              \
   template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);                                        \
-  template void launch_mdot_q<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t);               \
-  template void launch_update_mdot_q<T>(int64_t, const T*, int64_t, int, const double2*, T*, double2*,            \
-                                        hipStream_t);                                                             \
-  template void launch_update_norm_q<T>(int64_t, const T*, int64_t, int, const double2*, T*, double*, double*,    \
-                                        hipStream_t);
+  template void launch_update_norm<T>(int64_t, const T*, int64_t, int, const double2*, T*, double*, double*,      \
+                                      hipStream_t);
 EDDY_INST(double2)
 EDDY_INST(float2)
 #undef EDDY_INST
