@@ -8,7 +8,7 @@
 
 namespace eddy {
 
-constexpr int kRedBlocks = 512;       // blocks of the two-stage reductions
+constexpr int kRedBlocks = 2048;      // blocks of the two-stage reductions
 
 // ---- assembly (Section 2, Eqs. 5-7; Section 3 global blocks)
 void launch_element(int64_t nt, int64_t nct, const double* xyz, const int* tet, const int* region,
