@@ -63,6 +63,8 @@ typedef struct {
   double tau_gauge;    /* gauge penalty 1/mu~ (Eq. 3); > 0                        */
   double delta_v;      /* optional V penalty delta*sigma*V (Section 4); >= 0      */
   int32_t block_size;  /* block-Jacobi block size b, 1..64                         */
+  double tau_precond;  /* penalty inside the block-Jacobi blocks (a preconditioner */
+                       /* parameter: they must be invertible); 0 = tau_gauge      */
 } eddy_params;
 
 typedef struct {

@@ -54,7 +54,7 @@ using namespace eddy;
 struct eddy_op {
   int64_t nv, nt, ne, nc, nct, n, nnz, nnzw, nb;
   int32_t nreg, ncomp, bsize;
-  double tau, delta_v, omega = 0;
+  double tau, tau_p, delta_v, omega = 0;
   bool assembled = false;
   // static (uploaded at create)
   double* xyz;
@@ -69,7 +69,7 @@ struct eddy_op {
   double2 *val, *ebuf, *minv;
   double* gscr;                 // gauge part of the diagonal blocks (assembly scratch)
   float2 *val32, *minv32;       // complex64 copies for the mixed-precision inner loop
-  double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *lumped, *s, *nu_reg, *sig_reg;
+  double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *d0taup, *lumped, *s, *nu_reg, *sig_reg;
   double2 *tmp1, *tmp2, *tvec, *red;
   double* rred;
   int* status;
@@ -135,6 +135,7 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->rbuf = c.take<double>(6 * m->nt);
   o->d0 = c.take<double>(m->nv);
   o->d0tau = c.take<double>(m->nv);
+  o->d0taup = c.take<double>(m->nv);
   o->lumped = c.take<double>(m->nc);
   o->s = c.take<double>(m->ndof());
   o->nu_reg = c.take<double>(m->nreg);
@@ -152,6 +153,7 @@ eddy_status check_params(const eddy_params* p) {
   if (!p) { set_error("params is NULL"); return EDDY_ERR_ARG; }
   if (!(p->tau_gauge > 0)) { set_error("tau_gauge must be > 0"); return EDDY_ERR_ARG; }
   if (!(p->delta_v >= 0)) { set_error("delta_v must be >= 0"); return EDDY_ERR_ARG; }
+  if (!(p->tau_precond >= 0)) { set_error("tau_precond must be >= 0"); return EDDY_ERR_ARG; }
   if (p->block_size < 1 || p->block_size > kMaxBlock) { set_error("block_size must be in 1..64"); return EDDY_ERR_ARG; }
   return EDDY_OK;
 }
@@ -294,6 +296,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   o->nnz = m->nnz(); o->nnzw = m->nnzw(); o->nb = (int64_t)m->blk_ptr.size() - 1;
   o->nreg = m->nreg; o->ncomp = m->ncomp; o->bsize = p->block_size;
   o->tau = p->tau_gauge; o->delta_v = p->delta_v;
+  o->tau_p = p->tau_precond > 0 ? p->tau_precond : p->tau_gauge;
   o->is_cond = m->is_cond;
   hipStream_t s = (hipStream_t)stream;
   std::vector<int32_t> blk_of(o->n), loc_of(o->n);
@@ -347,12 +350,13 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   launch_gather_r(o->nv, o->d0ptr, o->d0list, o->vol4, o->d0, s);
   launch_gather_r(o->nc, o->lcptr, o->lclist, o->vol4, o->lumped, s);
   launch_d0tau(o->nv, o->d0, o->tau, o->d0tau, s);
+  launch_d0tau(o->nv, o->d0, o->tau_p, o->d0taup, s);
   launch_equilibrate(o->n, o->ne, o->diagpos, o->val, o->wrowptr, o->wcol, o->wval, o->d0tau, o->s, o->status, s);
   launch_scale_rows(o->n, o->rowptr, o->col, o->val, o->s, s);
   launch_scale_w(o->ne, o->wrowptr, o->wval, o->s, s);
   launch_permute_r(o->nnzw, o->wtperm, o->wval, o->wtval, s);
   launch_block_invert(o->nb, o->blk_ptr, o->blk_dofs, o->blk_of, o->loc_of, o->rowptr, o->col, o->val, o->ne,
-                      o->wrowptr, o->wcol, o->wval, o->d0tau, o->gscr, o->minv, o->status, s);
+                      o->wrowptr, o->wcol, o->wval, o->d0taup, o->gscr, o->minv, o->status, s);
   launch_to_c64(o->nnz, o->val, o->val32, s);
   launch_to_c64(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv32, s);
   HIP_TRY(hipGetLastError());

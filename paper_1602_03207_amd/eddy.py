@@ -22,7 +22,8 @@ class EddyError(RuntimeError):
 
 
 class _Params(C.Structure):
-    _fields_ = [("tau_gauge", C.c_double), ("delta_v", C.c_double), ("block_size", C.c_int32)]
+    _fields_ = [("tau_gauge", C.c_double), ("delta_v", C.c_double), ("block_size", C.c_int32),
+                ("tau_precond", C.c_double)]
 
 
 class _Opts(C.Structure):
@@ -186,11 +187,12 @@ def _aligned(nbytes: int, device):
 class Operator:
     """Device operator: workspace, assembly, RHS, solve and outputs."""
 
-    def __init__(self, mesh: Mesh, tau: float = 1.0, delta_v: float = 0.0, block_size: int = 64, device="cuda"):
+    def __init__(self, mesh: Mesh, tau: float = 1.0, delta_v: float = 0.0, block_size: int = 64, device="cuda",
+                 tau_precond: float = 0.0):
         import torch
         self.mesh = mesh
         self.device = torch.device(device)
-        self.params = _Params(tau, delta_v, block_size)
+        self.params = _Params(tau, delta_v, block_size, tau_precond)
         nbytes = C.c_size_t()
         _check(_lib.eddy_op_workspace_bytes(mesh._h, C.byref(self.params), C.byref(nbytes)), "eddy_op_workspace_bytes")
         self.ws_bytes = nbytes.value
