@@ -91,6 +91,8 @@ typedef struct {
   double div_residual; /* ||G^T b_A|| / ||b||: discrete divergence of the source   */
   int32_t precision_used;  /* 1 if the complex64 inner loop ran (mixed mode needs */
                            /* the penalty-free operator; else FP64 is used)        */
+  int32_t reorth_steps;    /* Arnoldi steps that needed the second Gram-Schmidt    */
+                           /* pass (norm dropped below 1/sqrt(2) of ||w||)         */
 } eddy_solve_report;
 
 /* ---- mesh (host) -------------------------------------------------------
@@ -143,8 +145,9 @@ eddy_status eddy_rhs_from_current(const eddy_op* op, const double* J_dev, eddy_c
                                   eddy_stream stream);
 
 /* ---- solve -------------------------------------------------------------
- * Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt
- * applied twice (CGS2), block-Jacobi preconditioning, on the equilibrated
+ * Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt and
+ * selective reorthogonalisation (a second pass whenever the first loses more
+ * than 1 - 1/sqrt(2) of the norm), block-Jacobi preconditioning, on the equilibrated
  * system; x0 = 0.  When delta_V = 0 and the source is divergence-free
  * (||G^T b_A|| <= 1e-10 ||b||, as Section 2 requires of the excitation), the
  * gauged solution has W^T A = 0, so GMRES iterates on the operator without

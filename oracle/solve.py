@@ -8,7 +8,9 @@
   the mass-weighted mean is removed afterwards (first option of Section 4).
 * ``gmres``: restarted, right-preconditioned GMRES(m) on the symmetrically
   equilibrated system D^-1/2 M D^-1/2 y = D^-1/2 b (D = |diag M|), with
-  classical Gram-Schmidt applied twice, complex Givens rotations for the
+  classical Gram-Schmidt with a second pass whenever the first drops the
+  norm below 1/sqrt(2) of its value ("twice is enough"), complex Givens
+  rotations for the
   Hessenberg least-squares problem, and block-Jacobi preconditioning.  The
   stopping test is on the true equilibrated residual, i.e. the residual in
   the D^-1/2-weighted norm.
@@ -92,7 +94,8 @@ class BlockJacobi:
     inv: dict = field(default_factory=dict)     # size -> (block index array, inverses [k, s, s])
 
     @classmethod
-    def build(cls, sysm: System, xyz: np.ndarray, b: int, scale: np.ndarray | None = None):
+    def build(cls, sysm: System, xyz: np.ndarray, b: int, scale: np.ndarray | None = None,
+              tau_precond: float | None = None):
         topo = sysm.topo
         blocks = rcb_blocks(dof_coords(xyz, topo.edges, topo.cond_nodes), b)
         Mng = sysm.matrix_no_gauge().tocsr()
@@ -107,7 +110,7 @@ class BlockJacobi:
                 Wi = Wc[Ia]
                 G = (Wi @ sp.diags(dinv) @ Wi.T).toarray()
                 na = Ia.size                              # A DOFs come first (sorted ids)
-                Mb[:na, :na] += sysm.tau * G
+                Mb[:na, :na] += (sysm.tau if tau_precond is None else tau_precond) * G
             if scale is not None:
                 Mb = scale[I][:, None] * Mb * scale[I][None, :]
             by_size.setdefault(I.size, []).append((k, Mb))
@@ -150,7 +153,8 @@ def _givens(a: complex, b: complex):
 
 def gmres(matvec, b: np.ndarray, precond, m: int = 30, tol: float = 1e-10, max_iter: int = 5000,
           x0: np.ndarray | None = None) -> GmresResult:
-    """Right-preconditioned restarted GMRES(m) with CGS2 (plain, unblocked)."""
+    """Right-preconditioned restarted GMRES(m), classical Gram-Schmidt with
+    selective reorthogonalisation (plain, unblocked)."""
     n = b.size
     x = np.zeros(n, dtype=complex) if x0 is None else x0.astype(complex).copy()
     bnorm = np.linalg.norm(b)
@@ -172,12 +176,16 @@ def gmres(matvec, b: np.ndarray, precond, m: int = 30, tol: float = 1e-10, max_i
         k = 0
         for j in range(m):
             w = matvec(precond(V[j]))
+            w0 = np.linalg.norm(w)
             h1 = V[: j + 1].conj() @ w
             w = w - V[: j + 1].T @ h1
-            h2 = V[: j + 1].conj() @ w
-            w = w - V[: j + 1].T @ h2
-            H[: j + 1, j] = h1 + h2
             hn = np.linalg.norm(w)
+            h2 = np.zeros_like(h1)
+            if hn < w0 / np.sqrt(2.0):
+                h2 = V[: j + 1].conj() @ w
+                w = w - V[: j + 1].T @ h2
+                hn = np.linalg.norm(w)
+            H[: j + 1, j] = h1 + h2
             H[j + 1, j] = hn
             if hn != 0.0:
                 V[j + 1] = w / hn
@@ -229,7 +237,8 @@ def coulomb_projection(sysm: System, x: np.ndarray) -> np.ndarray:
 
 
 def solve_gmres(sysm: System, xyz: np.ndarray, b: np.ndarray, block: int = 64, m: int = 30,
-                tol: float = 1e-10, max_iter: int = 5000, gauge_in_operator: bool | None = None):
+                tol: float = 1e-10, max_iter: int = 5000, gauge_in_operator: bool | None = None,
+                tau_precond: float | None = None):
     """Plain FP64 method: equilibrate, block-Jacobi, GMRES(m); returns (x, result).
 
     gauge_in_operator=None picks the penalty-free iteration + Coulomb
@@ -238,7 +247,7 @@ def solve_gmres(sysm: System, xyz: np.ndarray, b: np.ndarray, block: int = 64, m
     system at the returned x.
     """
     s = equilibration(sysm)
-    P = BlockJacobi.build(sysm, xyz, block, scale=s)
+    P = BlockJacobi.build(sysm, xyz, block, scale=s, tau_precond=tau_precond)
     if gauge_in_operator is None:
         gauge_in_operator = not (sysm.delta_v == 0.0 and divergence_residual(sysm, b) <= 1e-10)
     if gauge_in_operator:

@@ -434,7 +434,8 @@ struct SolveWs {
   double* cdiag;
   // device Hessenberg least squares
   double2 *Hd, *snd, *gd;
-  double *csd, *est;
+  double *csd, *est, *nrm1;
+  int *flag, *nreorth;
 };
 size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne, int precision) {
   Carve c(base);
@@ -455,6 +456,9 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->gd = c.take<double2>(m + 2);
   w->csd = c.take<double>(m + 1);
   w->est = c.take<double>(m + 1);
+  w->nrm1 = c.take<double>(8);
+  w->flag = c.take<int>(8);
+  w->nreorth = c.take<int>(8);
   w->V = c.take<double2>(mixed ? 0 : (int64_t)(m + 1) * n);
   w->w = c.take<double2>(n);
   w->z = c.take<double2>(n);
@@ -527,12 +531,14 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       if (o->profile) (void)hipEventRecord(ev[3], s);
       // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, ||w|| (FP64 accumulation)
       const int q = j + 1;
-      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
-      launch_reduce_cols(q, W.part, W.h1, s);
-      launch_update(n, (const T*)I.V, n, q, W.h1, I.w, s);
-      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s);
-      launch_reduce_cols(q, W.part, W.h2, s);
-      launch_update_norm(n, (const T*)I.V, n, q, W.h2, I.w, W.rpart, W.nrm, s);
+      // first pass (+ ||w||^2), then the second pass only when needed
+      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s, 1);
+      launch_reduce_cols(q + 1, W.part, W.h1, s);
+      launch_update_norm(n, (const T*)I.V, n, q, W.h1, I.w, W.rpart, W.nrm1, s);
+      launch_reorth_decide(q, W.h1, W.nrm1, W.h2, W.nrm, W.flag, W.nreorth, s);
+      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s, 0, W.flag);
+      launch_reduce_cols(q, W.part, W.h2, s, W.flag);
+      launch_update_norm(n, (const T*)I.V, n, q, W.h2, I.w, W.rpart, W.nrm, s, W.flag);
       launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * n, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
       launch_givens(j, m, W.h1, W.h2, W.nrm, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est, s);
@@ -646,6 +652,7 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
     if (R.div_residual > 1e-10) gauge_op = true;
   }
   R.gauge_in_operator = gauge_op ? 1 : 0;
+  HIP_TRY(hipMemsetAsync(W.nreorth, 0, sizeof(int), s));
   // equilibrated right-hand side b~ = s b, x~ = 0
   launch_diag_scale(n, (const double2*)b_dev, o->s, 0, W.bt, s);
   launch_zero(n, W.xt, s);
@@ -725,6 +732,8 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   R.iters = it;
+  HIP_TRY(hipMemcpyAsync(&R.reorth_steps, W.nreorth, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   R.converged = R.relres <= opts->tol ? 1 : 0;
   R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = R;

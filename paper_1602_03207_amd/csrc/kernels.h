@@ -46,9 +46,14 @@ template <class T>
 void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, const T* r, T* z,
                         hipStream_t st);
 // Krylov primitives: storage T, all reductions and Hessenberg entries in FP64
+// partial dots V^H w (+ ||w||^2 in slot q if want_norm); flag (device, may be
+// null) = 0 skips the launch
 template <class T>
-void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st);
-void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st);
+void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st,
+                 int want_norm = 0, const int* flag = nullptr);
+void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st, const int* flag = nullptr);
+void launch_reorth_decide(int q, const double2* h1, const double* nrm1, double2* h2, double* nrm, int* flag,
+                          int* counter, hipStream_t st);
 template <class T>
 void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, hipStream_t st);
 template <class T>
@@ -65,7 +70,7 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
 // second CGS2 update fused with the norm of the new vector
 template <class T>
 void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
-                        double* out_norm, hipStream_t st);
+                        double* out_norm, hipStream_t st, const int* flag = nullptr);
 // Hessenberg least squares on the device
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);

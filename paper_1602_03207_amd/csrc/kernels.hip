@@ -621,18 +621,25 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int*
   z[dof] = acc;
 }
 
-// partial[(c*8+k) * kRedBlocks + blockIdx.x] = sum_i conj(V_{c*8+k}[i]) w[i]  (FP64 accumulation)
+// partial[(c*8+k) * kRedBlocks + blockIdx.x] = sum_i conj(V_{c*8+k}[i]) w[i]  (FP64 accumulation).
+// With want_norm, the y = 0 slice also writes sum_i |w_i|^2 to slot q.  A
+// non-null flag equal to 0 skips the launch (conditional second CGS pass).
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                   const T* __restrict__ w, double2* __restrict__ partial) {
+                                                   const T* __restrict__ w, double2* __restrict__ partial,
+                                                   int want_norm, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
   __shared__ double sh[4];
   const int c0 = blockIdx.y * 8;
   const int cnt = min(8, q - c0);
+  const bool nrm = want_norm && blockIdx.y == 0;
   double2 acc[8];
+  double ww = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[k] = make_double2(0.0, 0.0);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double2 wi = ld2(w[i]);
+    if (nrm) ww = fma(wi.x, wi.x, fma(wi.y, wi.y, ww));
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if (k < cnt) acc[k] = cfma_conj(ld2(V[(int64_t)(c0 + k) * ldv + i]), wi, acc[k]);
@@ -642,11 +649,16 @@ __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restric
     const double im = block_sum(acc[k].y, sh);
     if (threadIdx.x == 0) partial[(int64_t)(c0 + k) * kRedBlocks + blockIdx.x] = make_double2(re, im);
   }
+  if (nrm) {
+    const double t = block_sum(ww, sh);
+    if (threadIdx.x == 0) partial[(int64_t)q * kRedBlocks + blockIdx.x] = make_double2(t, 0.0);
+  }
 }
 
 // out[k] = sum_b partial[k * kRedBlocks + b]  (fixed tree per column)
 __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restrict__ partial,
-                                                          double2* __restrict__ out) {
+                                                          double2* __restrict__ out, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
   __shared__ double sh[4];
   const int k = blockIdx.x;
   double re = 0.0, im = 0.0;
@@ -692,7 +704,8 @@ __global__ __launch_bounds__(kThreads) void k_norm2_partial(int64_t n, const T* 
 }
 
 __global__ __launch_bounds__(kThreads) void k_norm2_final(const double* __restrict__ partial,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
   __shared__ double sh[4];
   double acc = 0.0;
   for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) acc += partial[b];
@@ -745,7 +758,8 @@ __global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restric
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_update_norm(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
                                                           const double2* __restrict__ h, T* __restrict__ w,
-                                                          double* __restrict__ rpart) {
+                                                          double* __restrict__ rpart, const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
   __shared__ double2 hs[kMaxRestart + 1];
   __shared__ double sh[4];
   if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
@@ -766,6 +780,26 @@ __global__ __launch_bounds__(kThreads) void k_update_norm(int64_t n, const T* __
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) rpart[blockIdx.x] = acc;
+}
+
+// Selective reorthogonalisation: after one classical Gram-Schmidt pass the
+// second pass is needed only if the norm dropped below ||w|| / sqrt(2)
+// (twice is enough).  h1[q] holds ||w||^2 before the pass, nrm1 the norm
+// after it.  flag = 1 runs the second pass (which writes h2 and nrm);
+// otherwise h2 = 0 and nrm = nrm1.  counter counts second passes.
+__global__ void k_reorth_decide(int q, const double2* __restrict__ h1, const double* __restrict__ nrm1,
+                                double2* __restrict__ h2, double* __restrict__ nrm, int* __restrict__ flag,
+                                int* __restrict__ counter) {
+  const int t = threadIdx.x;
+  const double w0 = sqrt(h1[q].x);
+  const int need = nrm1[0] < 0.70710678118654752 * w0 ? 1 : 0;
+  if (t == 0) {
+    *flag = need;
+    if (need) counter[0] += 1;
+    else nrm[0] = nrm1[0];
+  }
+  if (!need)
+    for (int k = t; k < q; k += blockDim.x) h2[k] = make_double2(0.0, 0.0);
 }
 
 // ---- Hessenberg least squares on the device (one thread) ----
@@ -970,12 +1004,17 @@ void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, con
   k_block_apply<T><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
 }
 template <class T>
-void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st) {
+void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st,
+                 int want_norm, const int* flag) {
   dim3 grid(kRedBlocks, (q + 7) / 8);
-  k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial);
+  k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial, want_norm, flag);
 }
-void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st) {
-  k_reduce_cols<<<q, kThreads, 0, st>>>(partial, out);
+void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st, const int* flag) {
+  k_reduce_cols<<<q, kThreads, 0, st>>>(partial, out, flag);
+}
+void launch_reorth_decide(int q, const double2* h1, const double* nrm1, double2* h2, double* nrm, int* flag,
+                          int* counter, hipStream_t st) {
+  k_reorth_decide<<<1, 64, 0, st>>>(q, h1, nrm1, h2, nrm, flag, counter);
 }
 template <class T>
 void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, hipStream_t st) {
@@ -984,7 +1023,7 @@ void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, 
 template <class T>
 void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipStream_t st) {
   k_norm2_partial<T><<<kRedBlocks, kThreads, 0, st>>>(n, w, partial);
-  k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm);
+  k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm, nullptr);
 }
 template <class T>
 void launch_scale_by_inv(int64_t n, const T* w, const double* norm, T* v, hipStream_t st) {
@@ -1004,9 +1043,9 @@ void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
 }
 template <class T>
 void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
-                        double* out_norm, hipStream_t st) {
-  k_update_norm<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart);
-  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm);
+                        double* out_norm, hipStream_t st, const int* flag) {
+  k_update_norm<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart, flag);
+  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, flag);
 }
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st) {
@@ -1022,7 +1061,7 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   template void launch_spmv<T>(int64_t, int64_t, const int*, const int*, const T*, const int*, const int*,        \
                                const double*, const double2*, const T*, const double2*, T*, hipStream_t);         \
   template void launch_block_apply<T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t);      \
-  template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t);                 \
+  template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t, int, const int*); \
   template void launch_update<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);               \
   template void launch_norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                \
   template void launch_scale_by_inv<T>(int64_t, const T*, const double*, T*, hipStream_t);                        \
@@ -1030,7 +1069,7 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   template void launch_combine<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);              \
   template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);                                        \
   template void launch_update_norm<T>(int64_t, const T*, int64_t, int, const double2*, T*, double*, double*,      \
-                                      hipStream_t);
+                                      hipStream_t, const int*);
 EDDY_INST(double2)
 EDDY_INST(float2)
 #undef EDDY_INST
@@ -1046,7 +1085,7 @@ void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, 
 }
 void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st) {
   k_udot_partial<<<kRedBlocks, kThreads, 0, st>>>(n, a, b, partial);
-  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, out);
+  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, out, nullptr);
 }
 void launch_edge_divergence(int64_t nv, const int* wtrowptr, const int* wtcol, const int* edges, const double2* b,
                             double2* d, hipStream_t st) {

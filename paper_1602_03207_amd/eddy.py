@@ -34,7 +34,7 @@ class _Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("relres", C.c_double), ("est_relres", C.c_double),
                 ("seconds", C.c_double), ("gauge_in_operator", C.c_int32), ("cg_iters", C.c_int32),
-                ("div_residual", C.c_double), ("precision_used", C.c_int32)]
+                ("div_residual", C.c_double), ("precision_used", C.c_int32), ("reorth_steps", C.c_int32)]
 
 
 EXPORTS = [
@@ -175,6 +175,7 @@ class SolveReport:
     cg_iters: int = 0
     div_residual: float = 0.0
     precision_used: int = 0
+    reorth_steps: int = 0
 
 
 def _aligned(nbytes: int, device):
@@ -243,7 +244,7 @@ class Operator:
                                     C.byref(rep), _stream()), "eddy_solve")
         return x, SolveReport(rep.iters, rep.restarts, bool(rep.converged), bool(rep.breakdown), rep.relres,
                               rep.est_relres, rep.seconds, bool(rep.gauge_in_operator), rep.cg_iters,
-                              rep.div_residual, rep.precision_used)
+                              rep.div_residual, rep.precision_used, rep.reorth_steps)
 
     def spmv(self, x, out=None):
         y = self._c128() if out is None else out

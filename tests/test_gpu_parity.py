@@ -245,3 +245,23 @@ def test_mixed_precision_c1_matches_oracle():
     x64, rep64 = op.solve(b, tol=1e-11)
     # the complex64 inner loop costs a few extra cycles at most
     assert rep.iters <= 2 * rep64.iters + 60
+
+
+def test_tau_precond_changes_only_the_preconditioner():
+    """A different penalty inside the blocks changes the iteration path, not
+    the solution; the oracle with the same blocks takes the same steps."""
+    from oracle.solve import direct, solve_gmres
+    from oracle.post import remove_v_mean
+    from paper_1602_03207_amd import eddy
+    m, s, op, J = case("c1")
+    M = eddy.Mesh(m.xyz, m.tet, m.region, [0, 1])
+    op2 = eddy.Operator(M, tau=1.0, block_size=64, tau_precond=0.1)
+    op2.assemble(np.array([1.0, 1.0]), np.array([0.0, 1.0]), 50.0)
+    b = op2.rhs_from_current(torch.from_numpy(J).cuda())
+    x, rep = op2.solve(b, tol=1e-12)
+    xo = remove_v_mean(s, direct(s, s.rhs(J)))
+    assert rep.converged
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
+    _, res = solve_gmres(s, m.xyz, s.rhs(J), block=64, m=30, tol=1e-10, tau_precond=0.1)
+    _, rep10 = op2.solve(b, tol=1e-10)
+    assert abs(rep10.iters - res.iters) <= max(2, 0.05 * res.iters)
