@@ -437,10 +437,12 @@ struct SolveWs {
   double *csd, *est, *nrm1;
   int *flag, *nreorth;
 };
+inline int64_t basis_ld(int64_t n) { return (n + 63) / 64 * 64; }   // 512-B aligned basis vectors
+
 size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne, int precision) {
   Carve c(base);
   const bool mixed = precision == 1;
-  w->V32 = c.take<float2>(mixed ? (int64_t)(m + 1) * n : 0);
+  w->V32 = c.take<float2>(mixed ? (int64_t)(m + 1) * basis_ld(n) : 0);
   w->w32 = c.take<float2>(mixed ? n : 0);
   w->z32 = c.take<float2>(mixed ? n : 0);
   w->psi = c.take<double2>(nv);
@@ -459,7 +461,7 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->nrm1 = c.take<double>(8);
   w->flag = c.take<int>(8);
   w->nreorth = c.take<int>(8);
-  w->V = c.take<double2>(mixed ? 0 : (int64_t)(m + 1) * n);
+  w->V = c.take<double2>(mixed ? 0 : (int64_t)(m + 1) * basis_ld(n));
   w->w = c.take<double2>(n);
   w->z = c.take<double2>(n);
   w->xt = c.take<double2>(n);
@@ -503,6 +505,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
                       double bnorm, int& it, eddy_solve_report& R, hipStream_t s) {
   const int m = opts->restart;
   const int64_t n = o->n;
+  const int64_t ld = basis_ld(n);
   double hbuf[8];
   eddy_status st;
   auto read_norm = [&](double* out) -> eddy_status {
@@ -519,7 +522,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
     int k = 0, jstart = 0;
     bool stop = false;
     for (int j = 0; j < m; ++j) {
-      T* vj = I.V + (int64_t)j * n;
+      T* vj = I.V + (int64_t)j * ld;
       hipEvent_t* ev = o->ev + 5 * (j - jstart);
       if (o->profile) (void)hipEventRecord(ev[0], s);
       launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, vj, I.z, s);
@@ -532,14 +535,14 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, ||w|| (FP64 accumulation)
       const int q = j + 1;
       // first pass (+ ||w||^2), then the second pass only when needed
-      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s, 1);
+      launch_mdot(n, (const T*)I.V, ld, q, (const T*)I.w, W.part, s, 1);
       launch_reduce_cols(q + 1, W.part, W.h1, s);
-      launch_update_norm(n, (const T*)I.V, n, q, W.h1, I.w, W.rpart, W.nrm1, s);
+      launch_update_norm(n, (const T*)I.V, ld, q, W.h1, I.w, W.rpart, W.nrm1, s);
       launch_reorth_decide(q, W.h1, W.nrm1, W.h2, W.nrm, W.flag, W.nreorth, s);
-      launch_mdot(n, (const T*)I.V, n, q, (const T*)I.w, W.part, s, 0, W.flag);
+      launch_mdot(n, (const T*)I.V, ld, q, (const T*)I.w, W.part, s, 0, W.flag);
       launch_reduce_cols(q, W.part, W.h2, s, W.flag);
-      launch_update_norm(n, (const T*)I.V, n, q, W.h2, I.w, W.rpart, W.nrm, s, W.flag);
-      launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * n, s);
+      launch_update_norm(n, (const T*)I.V, ld, q, W.h2, I.w, W.rpart, W.nrm, s, W.flag);
+      launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * ld, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
       launch_givens(j, m, W.h1, W.h2, W.nrm, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est, s);
       ++it;
@@ -578,7 +581,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
     if (!stop) k = m;
     R.est_relres = est[k - 1];
     launch_backsolve(k, m, W.Hd, W.gd, W.yd, s);
-    launch_combine(n, (const T*)I.V, n, k, W.yd, I.w, s);
+    launch_combine(n, (const T*)I.V, ld, k, W.yd, I.w, s);
     launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, (const T*)I.w, I.z, s);
     launch_axpy(n, (const T*)I.z, W.xt, s);
     // FP64 true residual of the iterated operator: r = b~ - M~ x~

@@ -637,7 +637,28 @@ __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restric
   double ww = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[k] = make_double2(0.0, 0.0);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four rows per trip, loads issued before the arithmetic (more bytes in flight)
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    T wv[4], vv[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wv[u] = w[i + u * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < cnt)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) vv[u][k] = V[(int64_t)(c0 + k) * ldv + i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 wi = ld2(wv[u]);
+      if (nrm) ww = fma(wi.x, wi.x, fma(wi.y, wi.y, ww));
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < cnt) acc[k] = cfma_conj(ld2(vv[u][k]), wi, acc[k]);
+    }
+  }
+  for (; i < n; i += stride) {
     const double2 wi = ld2(w[i]);
     if (nrm) ww = fma(wi.x, wi.x, fma(wi.y, wi.y, ww));
 #pragma unroll
