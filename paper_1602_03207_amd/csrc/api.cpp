@@ -470,7 +470,7 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->h2 = c.take<double2>(kMaxRestart + 2);
   w->hd = c.take<double2>(kMaxRestart + 2);
   w->yd = c.take<double2>(kMaxRestart + 2);
-  w->part = c.take<double2>((int64_t)kRedBlocks * (kMaxRestart + 2));
+  w->part = c.take<double2>((int64_t)(mdot_parts(n > nv ? n : nv) + kRedBlocks) * (m + 2));
   w->rpart = c.take<double>(kRedBlocks + 8);
   w->nrm = c.take<double>(8);
   return c.off + 256;
@@ -536,11 +536,11 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       const int q = j + 1;
       // first pass (+ ||w||^2), then the second pass only when needed
       launch_mdot(n, (const T*)I.V, ld, q, (const T*)I.w, W.part, s, 1);
-      launch_reduce_cols(q + 1, W.part, W.h1, s);
+      launch_reduce_cols(q + 1, mdot_parts(n), W.part, W.h1, s);
       launch_update_norm(n, (const T*)I.V, ld, q, W.h1, I.w, W.rpart, W.nrm1, s);
       launch_reorth_decide(q, W.h1, W.nrm1, W.h2, W.nrm, W.flag, W.nreorth, s);
       launch_mdot(n, (const T*)I.V, ld, q, (const T*)I.w, W.part, s, 0, W.flag);
-      launch_reduce_cols(q, W.part, W.h2, s, W.flag);
+      launch_reduce_cols(q, mdot_parts(n), W.part, W.h2, s, W.flag);
       launch_update_norm(n, (const T*)I.V, ld, q, W.h2, I.w, W.rpart, W.nrm, s, W.flag);
       launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * ld, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
@@ -697,18 +697,18 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
       launch_jacobi(nv, W.cr, W.cdiag, W.cz, s);
       HIP_TRY(hipMemcpyAsync(W.cp, W.cz, sizeof(double2) * nv, hipMemcpyDeviceToDevice, s));
       launch_mdot(nv, W.cr, nv, 1, W.cz, W.part, s);
-      launch_reduce_cols(1, W.part, W.cs + 0, s);
+      launch_reduce_cols(1, mdot_parts(nv), W.part, W.cs + 0, s);
       int cur = 0;
       const int kMaxCg = 20000;
       for (int ci = 1; ci <= kMaxCg; ++ci) {
         launch_grad_scaled(o->ne, o->edges, W.cp, o->s, W.cg, s);
         launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, W.cg, W.cq, s);
         launch_mdot(nv, W.cp, nv, 1, W.cq, W.part, s);
-        launch_reduce_cols(1, W.part, W.cs + 2, s);
+        launch_reduce_cols(1, mdot_parts(nv), W.part, W.cs + 2, s);
         launch_cg_step(nv, W.cs + cur, W.cs + 2, W.cp, W.cq, W.psi, W.cr, s);
         launch_jacobi(nv, W.cr, W.cdiag, W.cz, s);
         launch_mdot(nv, W.cr, nv, 1, W.cz, W.part, s);
-        launch_reduce_cols(1, W.part, W.cs + (1 - cur), s);
+        launch_reduce_cols(1, mdot_parts(nv), W.part, W.cs + (1 - cur), s);
         launch_cg_dir(nv, W.cs + (1 - cur), W.cs + cur, W.cz, W.cp, s);
         cur = 1 - cur;
         R.cg_iters = ci;

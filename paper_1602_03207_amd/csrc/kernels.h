@@ -51,7 +51,10 @@ void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, con
 template <class T>
 void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st,
                  int want_norm = 0, const int* flag = nullptr);
-void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st, const int* flag = nullptr);
+// number of per-block partials launch_mdot writes per vector for length n
+int mdot_parts(int64_t n);
+void launch_reduce_cols(int q, int nparts, const double2* partial, double2* out, hipStream_t st,
+                        const int* flag = nullptr);
 void launch_reorth_decide(int q, const double2* h1, const double* nrm1, double2* h2, double* nrm, int* flag,
                           int* counter, hipStream_t st);
 template <class T>

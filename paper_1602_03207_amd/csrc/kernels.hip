@@ -34,6 +34,12 @@ inline unsigned blocks_for(int64_t n, int per = kThreads) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+// Sum over the 64 lanes of a wavefront (fixed butterfly).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Deterministic sum over a 256-thread block (fixed shuffle tree, then the 4
 // wave totals in order).  Result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -624,68 +630,64 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int*
 // partial[(c*8+k) * kRedBlocks + blockIdx.x] = sum_i conj(V_{c*8+k}[i]) w[i]  (FP64 accumulation).
 // With want_norm, the y = 0 slice also writes sum_i |w_i|^2 to slot q.  A
 // non-null flag equal to 0 skips the launch (conditional second CGS pass).
+// Each workgroup owns 512 consecutive rows (two per thread) and the 8
+// vectors c0..c0+7 of slice blockIdx.y; per-block sums go to
+// partial[(c0+k) * gridDim.x + blockIdx.x].  With want_norm, slice 0 also
+// writes sum |w|^2 to slot q.  A non-null flag equal to 0 skips the launch.
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
                                                    const T* __restrict__ w, double2* __restrict__ partial,
                                                    int want_norm, const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
-  __shared__ double sh[4];
+  __shared__ double2 red[4][9];
   const int c0 = blockIdx.y * 8;
   const int cnt = min(8, q - c0);
   const bool nrm = want_norm && blockIdx.y == 0;
-  double2 acc[8];
-  double ww = 0.0;
+  const int64_t i0 = (int64_t)blockIdx.x * (2 * kThreads) + threadIdx.x;
+  const int64_t i1 = i0 + kThreads;
+  const bool a0 = i0 < n, a1 = i1 < n;
+  const double2 w0 = a0 ? ld2(w[i0]) : make_double2(0.0, 0.0);
+  const double2 w1 = a1 ? ld2(w[i1]) : make_double2(0.0, 0.0);
+  double2 acc[9];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = make_double2(0.0, 0.0);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // four rows per trip, loads issued before the arithmetic (more bytes in flight)
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    T wv[4], vv[4][8];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) wv[u] = w[i + u * stride];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < cnt)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) vv[u][k] = V[(int64_t)(c0 + k) * ldv + i + u * stride];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double2 wi = ld2(wv[u]);
-      if (nrm) ww = fma(wi.x, wi.x, fma(wi.y, wi.y, ww));
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k < cnt) acc[k] = cfma_conj(ld2(vv[u][k]), wi, acc[k]);
+  for (int k = 0; k < 8; ++k) {
+    acc[k] = make_double2(0.0, 0.0);
+    if (k < cnt) {
+      const T* Vk = V + (int64_t)(c0 + k) * ldv;
+      if (a0) acc[k] = cfma_conj(ld2(Vk[i0]), w0, acc[k]);
+      if (a1) acc[k] = cfma_conj(ld2(Vk[i1]), w1, acc[k]);
     }
   }
-  for (; i < n; i += stride) {
-    const double2 wi = ld2(w[i]);
-    if (nrm) ww = fma(wi.x, wi.x, fma(wi.y, wi.y, ww));
+  acc[8] = make_double2(w0.x * w0.x + w0.y * w0.y + w1.x * w1.x + w1.y * w1.y, 0.0);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int nk = nrm ? 9 : 8;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < cnt) acc[k] = cfma_conj(ld2(V[(int64_t)(c0 + k) * ldv + i]), wi, acc[k]);
-  }
-  for (int k = 0; k < cnt; ++k) {
-    const double re = block_sum(acc[k].x, sh);
-    const double im = block_sum(acc[k].y, sh);
-    if (threadIdx.x == 0) partial[(int64_t)(c0 + k) * kRedBlocks + blockIdx.x] = make_double2(re, im);
-  }
-  if (nrm) {
-    const double t = block_sum(ww, sh);
-    if (threadIdx.x == 0) partial[(int64_t)q * kRedBlocks + blockIdx.x] = make_double2(t, 0.0);
+  for (int k = 0; k < 9; ++k)
+    if (k < nk && (k < cnt || k == 8)) {
+      const double re = wave_sum(acc[k].x), im = wave_sum(acc[k].y);
+      if (ln == 0) red[wv][k] = make_double2(re, im);
+    }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int slot = t < cnt ? t : (nrm && t == 8 ? 8 : -1);
+  if (slot >= 0) {
+    const double2 r = make_double2((red[0][slot].x + red[1][slot].x) + (red[2][slot].x + red[3][slot].x),
+                                   (red[0][slot].y + red[1][slot].y) + (red[2][slot].y + red[3][slot].y));
+    const int col = slot == 8 ? q : c0 + slot;
+    partial[(int64_t)col * gridDim.x + blockIdx.x] = r;
   }
 }
 
 // out[k] = sum_b partial[k * kRedBlocks + b]  (fixed tree per column)
-__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restrict__ partial,
+__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restrict__ partial, int nparts,
                                                           double2* __restrict__ out, const int* __restrict__ flag) {
   if (flag && *flag == 0) return;
   __shared__ double sh[4];
   const int k = blockIdx.x;
   double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) {
-    re += partial[(int64_t)k * kRedBlocks + b].x;
-    im += partial[(int64_t)k * kRedBlocks + b].y;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    re += partial[(int64_t)k * nparts + b].x;
+    im += partial[(int64_t)k * nparts + b].y;
   }
   re = block_sum(re, sh);
   im = block_sum(im, sh);
@@ -1024,14 +1026,15 @@ void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, con
                         hipStream_t st) {
   k_block_apply<T><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
 }
+int mdot_parts(int64_t n) { return (int)((n + 2 * kThreads - 1) / (2 * kThreads)); }
 template <class T>
 void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st,
                  int want_norm, const int* flag) {
-  dim3 grid(kRedBlocks, (q + 7) / 8);
+  dim3 grid(mdot_parts(n), (q + 7) / 8);
   k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial, want_norm, flag);
 }
-void launch_reduce_cols(int q, const double2* partial, double2* out, hipStream_t st, const int* flag) {
-  k_reduce_cols<<<q, kThreads, 0, st>>>(partial, out, flag);
+void launch_reduce_cols(int q, int nparts, const double2* partial, double2* out, hipStream_t st, const int* flag) {
+  k_reduce_cols<<<q, kThreads, 0, st>>>(partial, nparts, out, flag);
 }
 void launch_reorth_decide(int q, const double2* h1, const double* nrm1, double2* h2, double* nrm, int* flag,
                           int* counter, hipStream_t st) {
@@ -1106,7 +1109,7 @@ void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, 
 }
 void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st) {
   k_udot_partial<<<kRedBlocks, kThreads, 0, st>>>(n, a, b, partial);
-  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, out, nullptr);
+  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, kRedBlocks, out, nullptr);
 }
 void launch_edge_divergence(int64_t nv, const int* wtrowptr, const int* wtcol, const int* edges, const double2* b,
                             double2* d, hipStream_t st) {
