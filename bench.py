@@ -29,6 +29,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    if the kernel source changed since those counters were taken."""
+    import hashlib
+    try:
+        d = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_1602_03207_amd", "csrc", "kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != d.get("kernels_hip_sha256"):
+        return None
+    return d.get("bytes_per_launch", {}).get(kernel)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,8 +213,10 @@ def main():
     if single:
         dom = max(single, key=lambda k: single[k]["total_ms"])
         d = single[dom]
-        roof = {"bound": "hbm", "kernel": knames[dom] + ("<float2>" if head == "mixed" else "<double2>"),
-                "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"], "traffic": None}
+        kname = knames[dom] + ("<float2>" if head == "mixed" else "<double2>")
+        roof = {"bound": "hbm", "kernel": kname, "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["frac"], "traffic": measured_traffic(kname),
+                "algorithmic_bytes": d["bytes_per_launch"]}
 
     cpu = None
     if not args.no_cpu_baseline and args.workload == "tube":
