@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scan", type=int, default=8,
+                    help="also time a batched scan of this many probe positions (0 = skip)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
                     help="headline method; 'both' also times plain FP64 for comparison")
     return ap.parse_args()
@@ -218,6 +220,39 @@ def main():
                 "frac": d["frac"], "traffic": measured_traffic(kname),
                 "algorithmic_bytes": d["bytes_per_launch"]}
 
+    scan = None
+    if args.scan and args.workload == "tube":
+        from synth import probe_currents
+        zs = np.linspace(-20e-3, 20e-3, args.scan)
+        Js = [torch.from_numpy(np.ascontiguousarray(probe_currents(m, float(z))[0])).cuda() for z in zs]
+        J2s = [torch.from_numpy(np.ascontiguousarray(probe_currents(m, float(z))[1])).cuda() for z in zs]
+        Bs = torch.empty((args.scan, op.ndof), dtype=torch.complex128, device="cuda")
+        B2s = torch.empty_like(Bs)
+        Xs = torch.empty_like(Bs)
+
+        def scan_step():
+            op.assemble(nu, sig, omega)
+            for k in range(args.scan):
+                op.rhs_from_current(Js[k], out=Bs[k])
+                op.rhs_from_current(J2s[k], out=B2s[k])
+            _, reps = op.solve_batched(Bs, tol=args.tol, restart=args.restart, max_iter=args.max_iter, out=Xs,
+                                       precision=head)
+            Zs = [op.impedance(Xs[k:k + 1], torch.stack([Bs[k], B2s[k]]), [1.0, 1.0]) for k in range(args.scan)]
+            return reps, Zs
+
+        scan_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sreps, sZ = scan_step()
+        torch.cuda.synchronize()
+        st = time.perf_counter() - t0
+        scan = {"positions": args.scan, "z_mm": [round(float(z) * 1e3, 3) for z in zs],
+                "s_per_position": round(st / args.scan, 4), "s_per_scan": round(st, 3),
+                "iters": [r.iters for r in sreps], "converged": all(r.converged for r in sreps),
+                "max_relres": max(r.relres for r in sreps),
+                "speedup_vs_single_headline": round(sec_per_solve / (st / args.scan), 3),
+                "Z11": [[z[0, 0].real, z[0, 0].imag] for z in sZ]}
+
     cpu = None
     if not args.no_cpu_baseline and args.workload == "tube":
         it_cpu = runs["fp64"]["rep"].iters if "fp64" in runs else rep.iters
@@ -252,6 +287,7 @@ def main():
                         "speedup_of_headline": round(runs["fp64"]["sec"] / sec_per_solve, 3),
                         "Z11": [runs["fp64"]["Z"][0, 0].real, runs["fp64"]["Z"][0, 0].imag],
                         "kernels": runs["fp64"]["kernels"]} if "fp64" in runs and head != "fp64" else None),
+        "batched_scan": scan,
         "host_setup_s": round(host_setup, 2),
         "kernels": kernels,
         "roofline": roof,

@@ -164,6 +164,22 @@ eddy_status eddy_solve_workspace_bytes(const eddy_op* op, const eddy_solve_opts*
 eddy_status eddy_solve(eddy_op* op, const eddy_c128* b_dev, eddy_c128* x_dev, const eddy_solve_opts* opts,
                        void* ws, size_t ws_bytes, eddy_solve_report* rep, eddy_stream stream);
 
+/* Batched solve: nrhs systems with the same operator, e.g. the probe
+ * positions of a scan (Section 3: one triangulation holds every probe
+ * position, only the right-hand side changes; Section 4: positions are
+ * independent).  Each system runs its own GMRES (same algorithm, options and
+ * result as eddy_solve); the SpMV and block-Jacobi launches serve every
+ * active system at once, reading the matrix and block inverses once per
+ * pass of up to 8 systems.  b_dev[nrhs][ndof], x_dev[nrhs][ndof] (device,
+ * no aliasing); rep[nrhs] (host) may be NULL.  Requires delta_V = 0 and
+ * divergence-free sources (EDDY_ERR_ARG otherwise).  ws: device workspace of
+ * at least eddy_solve_batched_workspace_bytes. */
+eddy_status eddy_solve_batched_workspace_bytes(const eddy_op* op, int32_t nrhs, const eddy_solve_opts* opts,
+                                               size_t* bytes);
+eddy_status eddy_solve_batched(eddy_op* op, int32_t nrhs, const eddy_c128* b_dev, eddy_c128* x_dev,
+                               const eddy_solve_opts* opts, void* ws, size_t ws_bytes, eddy_solve_report* rep,
+                               eddy_stream stream);
+
 /* ---- outputs -----------------------------------------------------------
  * Coil impedance Z[k*nsrc + l] (host) = -(i omega / (I_k I_l)) b_l^T A_k for
  * solutions x_dev[k*ndof ...] (k < nsol) and right-hand sides b_dev[l*ndof

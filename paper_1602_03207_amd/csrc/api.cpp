@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -489,6 +490,79 @@ eddy_status check_opts(const eddy_solve_opts* p) {
 
 namespace {
 
+// Buffers of the post-solve steps (projection CG and residual check).
+struct ProjBufs {
+  double2 *psi, *cr, *cz, *cp, *cq, *cg, *cs;
+  double* cdiag;
+  double2* part;
+  double *rpart, *nrm;
+  double2 *xtmp, *wtmp;   // n-vectors; xtmp may alias xt (consumed first)
+};
+
+// x = s x~; Coulomb projection when the penalty-free operator was iterated:
+// (W^T G) psi = W^T A by Jacobi-preconditioned CG on the nodes
+// (W^T A = W~^T x~), then A -= G psi, V += i omega psi|_c; finally the gauged
+// system's true weighted residual at x (into R.relres).
+eddy_status finish_solution(eddy_op* o, const ProjBufs& P, const double2* xt, const double2* bt, double2* x,
+                            double bnorm, bool gauge_op, eddy_solve_report& R, hipStream_t s) {
+  const int64_t n = o->n;
+  double hbuf[2];
+  auto read_norm = [&](double* out) -> eddy_status {
+    HIP_TRY(hipMemcpyAsync(hbuf, P.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = hbuf[0];
+    return EDDY_OK;
+  };
+  eddy_status st;
+  launch_diag_scale(n, xt, o->s, 0, x, s);
+  if (!gauge_op && bnorm > 0) {
+    const int64_t nv = o->nv;
+    launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, xt, P.cr, s);
+    launch_lap_diag(nv, o->wtrowptr, o->wtcol, o->wtval, o->edges, o->s, P.cdiag, s);
+    launch_zero(nv, P.psi, s);
+    launch_norm2(nv, P.cr, P.rpart, P.nrm, s);
+    double r0 = 0;
+    if ((st = read_norm(&r0)) != EDDY_OK) return st;
+    if (r0 > 0) {
+      launch_jacobi(nv, P.cr, P.cdiag, P.cz, s);
+      HIP_TRY(hipMemcpyAsync(P.cp, P.cz, sizeof(double2) * nv, hipMemcpyDeviceToDevice, s));
+      launch_mdot(nv, P.cr, nv, 1, P.cz, P.part, s);
+      launch_reduce_cols(1, mdot_parts(nv), P.part, P.cs + 0, s);
+      int cur = 0;
+      const int kMaxCg = 20000;
+      for (int ci = 1; ci <= kMaxCg; ++ci) {
+        launch_grad_scaled(o->ne, o->edges, P.cp, o->s, P.cg, s);
+        launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, P.cg, P.cq, s);
+        launch_mdot(nv, P.cp, nv, 1, P.cq, P.part, s);
+        launch_reduce_cols(1, mdot_parts(nv), P.part, P.cs + 2, s);
+        launch_cg_step(nv, P.cs + cur, P.cs + 2, P.cp, P.cq, P.psi, P.cr, s);
+        launch_jacobi(nv, P.cr, P.cdiag, P.cz, s);
+        launch_mdot(nv, P.cr, nv, 1, P.cz, P.part, s);
+        launch_reduce_cols(1, mdot_parts(nv), P.part, P.cs + (1 - cur), s);
+        launch_cg_dir(nv, P.cs + (1 - cur), P.cs + cur, P.cz, P.cp, s);
+        cur = 1 - cur;
+        R.cg_iters = ci;
+        if (ci % 25 == 0 || ci == kMaxCg) {
+          launch_norm2(nv, P.cr, P.rpart, P.nrm, s);
+          double rn = 0;
+          if ((st = read_norm(&rn)) != EDDY_OK) return st;
+          if (!(rn > 1e-13 * r0)) break;
+        }
+      }
+      launch_project(o->ne, o->nc, o->edges, o->cond_nodes, P.psi, o->omega, x, s);
+    }
+  }
+  if (bnorm > 0) {
+    launch_diag_scale(n, x, o->s, 1, P.xtmp, s);
+    op_spmv(o, P.xtmp, bt, P.wtmp, o->tvec, s, true);
+    launch_norm2(n, P.wtmp, P.rpart, P.nrm, s);
+    double beta = 0;
+    if ((st = read_norm(&beta)) != EDDY_OK) return st;
+    R.relres = beta / bnorm;
+  }
+  return EDDY_OK;
+}
+
 template <class T>
 struct Inner {
   T* V;
@@ -681,55 +755,8 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   } else {
     R.relres = 0;
   }
-  // x = s x~
-  launch_diag_scale(n, W.xt, o->s, 0, (double2*)x_dev, s);
-  if (!gauge_op && bnorm > 0) {
-    // Coulomb projection: (W^T G) psi = W^T A by Jacobi-preconditioned CG on
-    // the nodes (W^T A = W~^T x~), then A -= G psi, V += i omega psi|_c.
-    const int64_t nv = o->nv;
-    launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, W.xt, W.cr, s);
-    launch_lap_diag(nv, o->wtrowptr, o->wtcol, o->wtval, o->edges, o->s, W.cdiag, s);
-    launch_zero(nv, W.psi, s);
-    launch_norm2(nv, W.cr, W.rpart, W.nrm, s);
-    double r0 = 0;
-    if ((st = read_norm(&r0)) != EDDY_OK) return st;
-    if (r0 > 0) {
-      launch_jacobi(nv, W.cr, W.cdiag, W.cz, s);
-      HIP_TRY(hipMemcpyAsync(W.cp, W.cz, sizeof(double2) * nv, hipMemcpyDeviceToDevice, s));
-      launch_mdot(nv, W.cr, nv, 1, W.cz, W.part, s);
-      launch_reduce_cols(1, mdot_parts(nv), W.part, W.cs + 0, s);
-      int cur = 0;
-      const int kMaxCg = 20000;
-      for (int ci = 1; ci <= kMaxCg; ++ci) {
-        launch_grad_scaled(o->ne, o->edges, W.cp, o->s, W.cg, s);
-        launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, W.cg, W.cq, s);
-        launch_mdot(nv, W.cp, nv, 1, W.cq, W.part, s);
-        launch_reduce_cols(1, mdot_parts(nv), W.part, W.cs + 2, s);
-        launch_cg_step(nv, W.cs + cur, W.cs + 2, W.cp, W.cq, W.psi, W.cr, s);
-        launch_jacobi(nv, W.cr, W.cdiag, W.cz, s);
-        launch_mdot(nv, W.cr, nv, 1, W.cz, W.part, s);
-        launch_reduce_cols(1, mdot_parts(nv), W.part, W.cs + (1 - cur), s);
-        launch_cg_dir(nv, W.cs + (1 - cur), W.cs + cur, W.cz, W.cp, s);
-        cur = 1 - cur;
-        R.cg_iters = ci;
-        if (ci % 25 == 0 || ci == kMaxCg) {
-          launch_norm2(nv, W.cr, W.rpart, W.nrm, s);
-          double rn = 0;
-          if ((st = read_norm(&rn)) != EDDY_OK) return st;
-          if (!(rn > 1e-13 * r0)) break;
-        }
-      }
-      launch_project(o->ne, o->nc, o->edges, o->cond_nodes, W.psi, o->omega, (double2*)x_dev, s);
-    }
-  }
-  // true weighted residual of the gauged system at the returned x
-  if (bnorm > 0) {
-    launch_diag_scale(n, (const double2*)x_dev, o->s, 1, W.xt, s);
-    op_spmv(o, W.xt, W.bt, W.w, o->tvec, s, true);
-    launch_norm2(n, W.w, W.rpart, W.nrm, s);
-    if ((st = read_norm(&beta)) != EDDY_OK) return st;
-    R.relres = beta / bnorm;
-  }
+  ProjBufs P{W.psi, W.cr, W.cz, W.cp, W.cq, W.cg, W.cs, W.cdiag, W.part, W.rpart, W.nrm, W.xt, W.w};
+  if ((st = finish_solution(o, P, W.xt, W.bt, (double2*)x_dev, bnorm, gauge_op, R, s)) != EDDY_OK) return st;
   // remove the mass-weighted V mean per conductor component
   launch_vmean(o->nc, o->ncomp, o->comp, o->lumped, (double2*)x_dev + o->ne, o->red, s);
   HIP_TRY(hipGetLastError());
@@ -741,6 +768,273 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = R;
   return R.converged ? EDDY_OK : EDDY_WARN_NOT_CONVERGED;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of the batched solve: per-system Krylov state at fixed strides
+// plus one set of post-solve buffers reused system by system.
+struct BatchWs {
+  int nrhs, m;
+  int64_t ld;
+  void *V, *wT, *zT;                  // T-typed inner vectors
+  double2 *xt, *bt, *w64, *part, *h1, *h2, *Hd, *snd, *gd, *yd;
+  double *rpart, *nrm, *nrm1, *beta, *bnorm, *csd, *est;
+  int *flag, *nreorth, *kcols, *run, *cyc;
+  ProjBufs P;
+};
+
+size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, int precision) {
+  Carve c(base);
+  const int64_t n = o->n, ld = basis_ld(n), nv = o->nv, ne = o->ne;
+  const size_t tb = precision == 1 ? sizeof(float2) : sizeof(double2);
+  B->nrhs = nrhs;
+  B->m = m;
+  B->ld = ld;
+  B->V = c.take<char>((int64_t)nrhs * (m + 1) * ld * tb);
+  B->wT = c.take<char>((int64_t)nrhs * ld * tb);
+  B->zT = c.take<char>((int64_t)nrhs * ld * tb);
+  B->xt = c.take<double2>((int64_t)nrhs * ld);
+  B->bt = c.take<double2>((int64_t)nrhs * ld);
+  B->w64 = c.take<double2>((int64_t)nrhs * ld);
+  const int64_t np = mdot_parts(n > nv ? n : nv);
+  B->part = c.take<double2>((int64_t)nrhs * np * (m + 2));
+  B->h1 = c.take<double2>((int64_t)nrhs * (m + 2));
+  B->h2 = c.take<double2>((int64_t)nrhs * (m + 2));
+  B->Hd = c.take<double2>((int64_t)nrhs * (m + 1) * m);
+  B->snd = c.take<double2>((int64_t)nrhs * (m + 1));
+  B->gd = c.take<double2>((int64_t)nrhs * (m + 2));
+  B->yd = c.take<double2>((int64_t)nrhs * (m + 2));
+  B->rpart = c.take<double>((int64_t)nrhs * kRedBlocks);
+  B->nrm = c.take<double>(nrhs);
+  B->nrm1 = c.take<double>(nrhs);
+  B->beta = c.take<double>(nrhs);
+  B->bnorm = c.take<double>(nrhs);
+  B->csd = c.take<double>((int64_t)nrhs * (m + 1));
+  B->est = c.take<double>((int64_t)nrhs * (m + 1));
+  B->flag = c.take<int>(nrhs);
+  B->nreorth = c.take<int>(nrhs);
+  B->kcols = c.take<int>(nrhs);
+  B->run = c.take<int>(nrhs);
+  B->cyc = c.take<int>(nrhs);
+  ProjBufs& P = B->P;
+  P.psi = c.take<double2>(nv);
+  P.cr = c.take<double2>(nv);
+  P.cz = c.take<double2>(nv);
+  P.cp = c.take<double2>(nv);
+  P.cq = c.take<double2>(nv);
+  P.cg = c.take<double2>(ne);
+  P.cs = c.take<double2>(8);
+  P.cdiag = c.take<double>(nv);
+  P.part = B->part;
+  P.rpart = B->rpart;
+  P.nrm = c.take<double>(8);
+  P.xtmp = c.take<double2>(n);
+  P.wtmp = c.take<double2>(n);
+  return c.off + 256;
+}
+
+// Independent GMRES(m) processes for nrhs systems in lockstep cycles; the
+// SpMV and block-Jacobi launches serve every active system at once.
+template <class T>
+eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std::vector<double>& bnorm,
+                        std::vector<int>& its, std::vector<eddy_solve_report>& R, hipStream_t s) {
+  const int nrhs = B.nrhs, m = B.m;
+  const int64_t n = o->n, ld = B.ld, vstride = (int64_t)(m + 1) * ld, hs = m + 2;
+  const int64_t pstride = (int64_t)mdot_parts(n) * (m + 2);
+  T* V = (T*)B.V;
+  T* wT = (T*)B.wT;
+  T* zT = (T*)B.zT;
+  const T* val = std::is_same<T, float2>::value ? (const T*)o->val32 : (const T*)o->val;
+  const T* minv = std::is_same<T, float2>::value ? (const T*)o->minv32 : (const T*)o->minv;
+  std::vector<int> done(nrhs, 0), run(nrhs), cyc(nrhs), kc(nrhs);
+  std::vector<double> beta(bnorm), est((size_t)nrhs * (m + 1));
+  for (int r = 0; r < nrhs; ++r) done[r] = bnorm[r] > 0 ? 0 : 1;
+  HIP_TRY(hipMemcpyAsync(B.bnorm, bnorm.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+  const double2* rvec = B.bt;          // cycle start residual (FP64), x~ = 0 at first
+  while (true) {
+    int nact = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      cyc[r] = run[r] = done[r] ? 0 : 1;
+      nact += cyc[r];
+    }
+    if (!nact) break;
+    HIP_TRY(hipMemcpyAsync(B.cyc, cyc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(B.run, run.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(B.beta, beta.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+    // v0 = r / beta (stored in T)
+    launch_to_storage_b(n, rvec, ld, V, vstride, nrhs, s);
+    launch_scale_by_inv_b(n, (const T*)V, vstride, B.beta, V, vstride, B.cyc, nrhs, s);
+    int jstart = 0, jend = m;
+    for (int j = 0; j < m; ++j) {
+      const int q = j + 1;
+      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, vstride, (const T*)(V + (int64_t)j * ld), ld,
+                           zT, B.run, s);
+      launch_spmv_b(n, o->rowptr, o->col, val, nrhs, ld, (const T*)zT, (const T*)nullptr, wT, B.run, s);
+      launch_mdot_b(n, (const T*)V, ld, vstride, q, (const T*)wT, ld, B.part, pstride, 1, (const int*)nullptr, B.run,
+                    nrhs, s);
+      launch_reduce_cols_b(q + 1, mdot_parts(n), B.part, pstride, B.h1, hs, nullptr, B.run, nrhs, s);
+      launch_update_norm_b(n, (const T*)V, ld, vstride, q, B.h1, hs, wT, ld, B.rpart, B.nrm1, nullptr, B.run, nrhs,
+                           s);
+      launch_reorth_decide_b(q, B.h1, hs, B.nrm1, B.h2, B.nrm, B.flag, B.nreorth, B.run, nrhs, s);
+      launch_mdot_b(n, (const T*)V, ld, vstride, q, (const T*)wT, ld, B.part, pstride, 0, B.flag, B.run, nrhs, s);
+      launch_reduce_cols_b(q, mdot_parts(n), B.part, pstride, B.h2, hs, B.flag, B.run, nrhs, s);
+      launch_update_norm_b(n, (const T*)V, ld, vstride, q, B.h2, hs, wT, ld, B.rpart, B.nrm, B.flag, B.run, nrhs, s);
+      launch_scale_by_inv_b(n, (const T*)wT, ld, B.nrm, V + (int64_t)(j + 1) * ld, vstride, B.run, nrhs, s);
+      launch_givens_b(j, m, B.h1, B.h2, hs, B.nrm, B.Hd, B.csd, B.snd, B.gd, B.beta, B.bnorm, B.est, B.run, nrhs, s);
+      for (int r = 0; r < nrhs; ++r) its[r] += run[r];
+      bool any_max = false;
+      for (int r = 0; r < nrhs; ++r) any_max |= run[r] && its[r] >= opts->max_iter;
+      const bool check = (j + 1 - jstart) == kCheckEvery || j == m - 1 || any_max;
+      if (!check) continue;
+      HIP_TRY(hipMemcpyAsync(est.data(), B.est, sizeof(double) * est.size(), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      bool changed = false;
+      int nrun = 0;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!run[r]) continue;
+        for (int jj = jstart; jj <= j; ++jj) {
+          const double e = est[(size_t)r * (m + 1) + jj];
+          if (!std::isfinite(e)) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
+          if (e <= opts->tol) {
+            if (e == 0.0) R[r].breakdown = 1;
+            its[r] -= j - jj;
+            kc[r] = jj + 1;
+            run[r] = 0;
+            changed = true;
+            break;
+          }
+        }
+        if (run[r] && its[r] >= opts->max_iter) {
+          kc[r] = j + 1;
+          run[r] = 0;
+          changed = true;
+        }
+        nrun += run[r];
+      }
+      if (nrun == 0) {
+        jend = j + 1;
+        break;
+      }
+      if (changed) HIP_TRY(hipMemcpyAsync(B.run, run.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+      jstart = j + 1;
+    }
+    for (int r = 0; r < nrhs; ++r) {
+      if (run[r]) kc[r] = m;
+      if (cyc[r]) R[r].est_relres = est[(size_t)r * (m + 1) + (kc[r] - 1)];
+    }
+    (void)jend;
+    HIP_TRY(hipMemcpyAsync(B.kcols, kc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    launch_backsolve_b(B.kcols, m, B.Hd, B.gd, B.yd, hs, B.cyc, nrhs, s);
+    launch_combine_b(n, (const T*)V, ld, vstride, B.kcols, B.yd, hs, wT, ld, B.cyc, nrhs, s);
+    launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, ld, (const T*)wT, ld, zT, B.cyc, s);
+    launch_axpy_b(n, (const T*)zT, ld, B.xt, ld, B.cyc, nrhs, s);
+    // FP64 true residuals of the penalty-free operator
+    launch_spmv_b(n, o->rowptr, o->col, o->val, nrhs, ld, (const double2*)B.xt, (const double2*)B.bt, B.w64, B.cyc, s);
+    launch_norm2_b(n, (const double2*)B.w64, ld, B.rpart, B.nrm, B.cyc, nrhs, s);
+    std::vector<double> nr(nrhs);
+    HIP_TRY(hipMemcpyAsync(nr.data(), B.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r) {
+      if (!cyc[r]) continue;
+      beta[r] = nr[r];
+      R[r].restarts++;
+      R[r].relres = beta[r] / bnorm[r];
+      if (R[r].relres <= opts->tol || its[r] >= opts->max_iter || (R[r].breakdown && kc[r] < m)) done[r] = 1;
+    }
+    rvec = B.w64;
+  }
+  return EDDY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+eddy_status eddy_solve_batched_workspace_bytes(const eddy_op* o, int32_t nrhs, const eddy_solve_opts* opts,
+                                               size_t* bytes) {
+  if (!o || !bytes || nrhs < 1) { set_error("bad argument"); return EDDY_ERR_ARG; }
+  eddy_status st = check_opts(opts);
+  if (st != EDDY_OK) return st;
+  BatchWs B;
+  *bytes = carve_batch(&B, nullptr, o, nrhs, opts->restart, opts->precision);
+  return EDDY_OK;
+}
+
+eddy_status eddy_solve_batched(eddy_op* o, int32_t nrhs, const eddy_c128* b_dev, eddy_c128* x_dev,
+                               const eddy_solve_opts* opts, void* ws, size_t ws_bytes, eddy_solve_report* rep,
+                               eddy_stream stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!o || !b_dev || !x_dev || nrhs < 1) { set_error("bad argument"); return EDDY_ERR_ARG; }
+  if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+  eddy_status st = check_opts(opts);
+  if (st != EDDY_OK) return st;
+  BatchWs B;
+  const size_t need = carve_batch(&B, nullptr, o, nrhs, opts->restart, opts->precision);
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) {
+    set_error("batched solve workspace too small or misaligned: need " + std::to_string(need) + " bytes");
+    return EDDY_ERR_WORKSPACE;
+  }
+  carve_batch(&B, ws, o, nrhs, opts->restart, opts->precision);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = o->n, ld = B.ld;
+  if (o->delta_v != 0.0) { set_error("the batched solve needs delta_V = 0"); return EDDY_ERR_ARG; }
+  std::vector<eddy_solve_report> R(nrhs);
+  std::vector<double> bnorm(nrhs);
+  std::vector<int> its(nrhs, 0);
+  // every source must be divergence-free: the penalty-free operator is iterated
+  for (int r = 0; r < nrhs; ++r) {
+    const double2* br = (const double2*)b_dev + (int64_t)r * n;
+    launch_norm2(n, br, B.P.rpart, B.P.nrm, s);
+    double braw = 0, dn = 0;
+    HIP_TRY(hipMemcpyAsync(&braw, B.P.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    launch_edge_divergence(o->nv, o->wtrowptr, o->wtcol, o->edges, br, B.P.cr, s);
+    launch_norm2(o->nv, B.P.cr, B.P.rpart, B.P.nrm, s);
+    HIP_TRY(hipMemcpyAsync(&dn, B.P.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!std::isfinite(braw)) { set_error("right-hand side is not finite"); return EDDY_ERR_ARG; }
+    R[r].div_residual = braw > 0 ? dn / braw : 0.0;
+    if (R[r].div_residual > 1e-10) {
+      set_error("the batched solve needs divergence-free sources (system " + std::to_string(r) + ")");
+      return EDDY_ERR_ARG;
+    }
+  }
+  HIP_TRY(hipMemsetAsync(B.nreorth, 0, sizeof(int) * nrhs, s));
+  launch_diag_scale_b(n, (const double2*)b_dev, n, o->s, 0, B.bt, ld, nrhs, s);
+  for (int r = 0; r < nrhs; ++r) launch_zero(n, B.xt + (int64_t)r * ld, s);
+  launch_norm2_b(n, (const double2*)B.bt, ld, B.rpart, B.nrm, nullptr, nrhs, s);
+  HIP_TRY(hipMemcpyAsync(bnorm.data(), B.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (opts->precision == 1) st = run_batched<float2>(o, B, opts, bnorm, its, R, s);
+  else st = run_batched<double2>(o, B, opts, bnorm, its, R, s);
+  if (st != EDDY_OK) return st;
+  std::vector<int> reo(nrhs);
+  HIP_TRY(hipMemcpyAsync(reo.data(), B.nreorth, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    double2* xr = (double2*)x_dev + (int64_t)r * n;
+    if ((st = finish_solution(o, B.P, B.xt + (int64_t)r * ld, B.bt + (int64_t)r * ld, xr, bnorm[r], false, R[r], s)) !=
+        EDDY_OK)
+      return st;
+    launch_vmean(o->nc, o->ncomp, o->comp, o->lumped, xr + o->ne, o->red, s);
+    R[r].iters = its[r];
+    R[r].reorth_steps = reo[r];
+    R[r].precision_used = opts->precision;
+    R[r].converged = R[r].relres <= opts->tol ? 1 : 0;
+    all = all && R[r].converged;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < nrhs; ++r) {
+    R[r].seconds = secs;
+    if (rep) rep[r] = R[r];
+  }
+  return all ? EDDY_OK : EDDY_WARN_NOT_CONVERGED;
 }
 
 eddy_status eddy_profile(eddy_op* o, int32_t enable, double* ms, int64_t* counts) {

@@ -1,0 +1,66 @@
+// Device helpers shared by the HIP translation units (complex arithmetic on
+// double2/float2, deterministic wave/block reductions).  Included inside an
+// anonymous namespace by each .hip file.
+#pragma once
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + conj(a) * b
+__device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) {
+  return make_double2(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y)));
+}
+// acc + a * b
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+// acc + r * b (r real)
+__device__ __forceinline__ double2 rfma(double r, double2 b, double2 acc) {
+  return make_double2(fma(r, b.x, acc.x), fma(r, b.y, acc.y));
+}
+
+inline unsigned blocks_for(int64_t n, int per = kThreads) {
+  int64_t b = (n + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Sum over the 64 lanes of a wavefront (fixed butterfly).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic sum over a 256-thread block (fixed shuffle tree, then the 4
+// wave totals in order).  Result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+
+// ---- storage-type helpers: complex128 (double2) or complex64 (float2) ----
+__device__ __forceinline__ double2 ld2(double2 a) { return a; }
+__device__ __forceinline__ double2 ld2(float2 a) { return make_double2(a.x, a.y); }
+template <class T> __device__ __forceinline__ T st2(double2 a);
+template <> __device__ __forceinline__ double2 st2<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 st2<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+template <class T> __device__ __forceinline__ T zero2();
+template <> __device__ __forceinline__ double2 zero2<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float2 zero2<float2>() { return make_float2(0.f, 0.f); }
+// acc + a * b in the storage precision
+template <class T> __device__ __forceinline__ T cfmaT(T a, T b, T acc) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+  return acc;
+}
+

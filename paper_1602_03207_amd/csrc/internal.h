@@ -26,7 +26,8 @@ namespace eddy {
 constexpr int kLocalEdge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 constexpr int kMaxBlock = 64;       // block-Jacobi block size limit (LDS-resident inverse)
 constexpr int kMaxRestart = 64;
-constexpr int kMaxWRow = 32;       // max nodes adjacent to one edge (LDS-staged gauge blocks)
+constexpr int kMaxWRow = 32;
+constexpr int kBatchChunk = 8;     // systems per pass of the batched SpMV / block-Jacobi kernels       // max nodes adjacent to one edge (LDS-staged gauge blocks)
 
 inline int pair6(int l, int m) {    // upper-triangle slot of a symmetric 6x6
   if (l > m) { int t = l; l = m; m = t; }

@@ -74,6 +74,48 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
 template <class T>
 void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
                         double* out_norm, hipStream_t st, const int* flag = nullptr);
+// ---- batched systems (vectors of system r at offset r * stride; grid.z = r;
+// `active` (device int[nrhs], may be null) masks systems out)
+template <class T>
+void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, int nrhs,
+                          int64_t rstride, const T* r, int64_t zstride, T* z, const int* active, hipStream_t st);
+template <class T>
+void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, int nrhs, int64_t ld, const T* x,
+                   const T* b, T* y, const int* active, hipStream_t st);
+template <class T>
+void launch_mdot_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* w, int64_t wstride,
+                   double2* partial, int64_t pstride, int want_norm, const int* flag, const int* active, int nrhs,
+                   hipStream_t st);
+void launch_reduce_cols_b(int q, int nparts, const double2* partial, int64_t pstride, double2* out, int64_t ostride,
+                          const int* flag, const int* active, int nrhs, hipStream_t st);
+template <class T>
+void launch_update_norm_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* h,
+                          int64_t hstride, T* w, int64_t wstride, double* rpart, double* out_norm, const int* flag,
+                          const int* active, int nrhs, hipStream_t st);
+void launch_reorth_decide_b(int q, const double2* h1, int64_t hstride, const double* nrm1, double2* h2, double* nrm,
+                            int* flag, int* counter, const int* active, int nrhs, hipStream_t st);
+template <class T>
+void launch_norm2_b(int64_t n, const T* w, int64_t wstride, double* partial, double* out_norm, const int* active,
+                    int nrhs, hipStream_t st);
+template <class T>
+void launch_scale_by_inv_b(int64_t n, const T* w, int64_t wstride, const double* norm, T* v, int64_t vstride,
+                           const int* active, int nrhs, hipStream_t st);
+void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, const double* nrm,
+                     double2* H, double* cs, double2* sn, double2* g, const double* beta, const double* bnorm,
+                     double* est, const int* active, int nrhs, hipStream_t st);
+void launch_backsolve_b(const int* ks, int m, const double2* H, const double2* g, double2* y, int64_t ystride,
+                        const int* active, int nrhs, hipStream_t st);
+template <class T>
+void launch_combine_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, const int* qs, const double2* y,
+                      int64_t ystride, T* u, int64_t ustride, const int* active, int nrhs, hipStream_t st);
+template <class T>
+void launch_axpy_b(int64_t n, const T* z, int64_t zstride, double2* x, int64_t xstride, const int* active, int nrhs,
+                   hipStream_t st);
+void launch_diag_scale_b(int64_t n, const double2* in, int64_t istride, const double* s, int divide, double2* out,
+                         int64_t ostride, int nrhs, hipStream_t st);
+template <class T>
+void launch_to_storage_b(int64_t n, const double2* in, int64_t istride, T* out, int64_t ostride, int nrhs,
+                         hipStream_t st);
 // Hessenberg least squares on the device
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);

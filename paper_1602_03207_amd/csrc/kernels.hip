@@ -9,49 +9,8 @@
 namespace eddy {
 namespace {
 
-constexpr int kThreads = 256;
+#include "devmath.h"
 
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// acc + conj(a) * b
-__device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 acc) {
-  return make_double2(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y)));
-}
-// acc + a * b
-__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
-  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
-}
-// acc + r * b (r real)
-__device__ __forceinline__ double2 rfma(double r, double2 b, double2 acc) {
-  return make_double2(fma(r, b.x, acc.x), fma(r, b.y, acc.y));
-}
-
-inline unsigned blocks_for(int64_t n, int per = kThreads) {
-  int64_t b = (n + per - 1) / per;
-  return (unsigned)(b < 1 ? 1 : b);
-}
-
-// Sum over the 64 lanes of a wavefront (fixed butterfly).
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Deterministic sum over a 256-thread block (fixed shuffle tree, then the 4
-// wave totals in order).  Result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  if (l == 0) sh[w] = v;
-  __syncthreads();
-  double r = 0;
-  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  __syncthreads();
-  return r;
-}
 
 // ---------------------------------------------------------------------------
 // Element kernel: one thread per tetrahedron.  grad(l_1..3) are the columns
@@ -559,22 +518,6 @@ __global__ __launch_bounds__(kThreads) void k_project(int64_t ne, int64_t nc, co
   }
 }
 
-// ---- storage-type helpers: complex128 (double2) or complex64 (float2) ----
-__device__ __forceinline__ double2 ld2(double2 a) { return a; }
-__device__ __forceinline__ double2 ld2(float2 a) { return make_double2(a.x, a.y); }
-template <class T> __device__ __forceinline__ T st2(double2 a);
-template <> __device__ __forceinline__ double2 st2<double2>(double2 a) { return a; }
-template <> __device__ __forceinline__ float2 st2<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
-template <class T> __device__ __forceinline__ T zero2();
-template <> __device__ __forceinline__ double2 zero2<double2>() { return make_double2(0.0, 0.0); }
-template <> __device__ __forceinline__ float2 zero2<float2>() { return make_float2(0.f, 0.f); }
-// acc + a * b in the storage precision
-template <class T> __device__ __forceinline__ T cfmaT(T a, T b, T acc) {
-  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
-  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
-  return acc;
-}
-
 // y = M~ x (+ W~ t on A rows if wrowptr), 8 lanes per row; y = b - (...) if b.
 // Arithmetic in the storage precision T.
 template <class T>
@@ -637,8 +580,14 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int*
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
                                                    const T* __restrict__ w, double2* __restrict__ partial,
-                                                   int want_norm, const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+                                                   int want_norm, const int* __restrict__ flag, int64_t vstride,
+                                                   int64_t wstride, int64_t pstride, const int* __restrict__ active) {
+  // right-hand side z of a batch (grid.z); strides are 0 for a single system
+  const int z = blockIdx.z;
+  if ((active && !active[z]) || (flag && flag[z] == 0)) return;
+  V += z * vstride;
+  w += z * wstride;
+  partial += z * pstride;
   __shared__ double2 red[4][9];
   const int c0 = blockIdx.y * 8;
   const int cnt = min(8, q - c0);
@@ -680,8 +629,13 @@ __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restric
 
 // out[k] = sum_b partial[k * kRedBlocks + b]  (fixed tree per column)
 __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restrict__ partial, int nparts,
-                                                          double2* __restrict__ out, const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+                                                          double2* __restrict__ out, const int* __restrict__ flag,
+                                                          int64_t pstride, int64_t ostride,
+                                                          const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if ((active && !active[z]) || (flag && flag[z] == 0)) return;
+  partial += z * pstride;
+  out += z * ostride;
   __shared__ double sh[4];
   const int k = blockIdx.x;
   double re = 0.0, im = 0.0;
@@ -715,7 +669,12 @@ __global__ __launch_bounds__(kThreads) void k_update(int64_t n, const T* __restr
 
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_norm2_partial(int64_t n, const T* __restrict__ w,
-                                                            double* __restrict__ partial) {
+                                                            double* __restrict__ partial, int64_t wstride,
+                                                            const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if (active && !active[z]) return;
+  w += z * wstride;
+  partial += (int64_t)z * gridDim.x;
   __shared__ double sh[4];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -727,8 +686,12 @@ __global__ __launch_bounds__(kThreads) void k_norm2_partial(int64_t n, const T* 
 }
 
 __global__ __launch_bounds__(kThreads) void k_norm2_final(const double* __restrict__ partial,
-                                                          double* __restrict__ out, const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+                                                          double* __restrict__ out, const int* __restrict__ flag,
+                                                          const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if ((active && !active[z]) || (flag && flag[z] == 0)) return;
+  partial += (int64_t)z * kRedBlocks;
+  out += z;
   __shared__ double sh[4];
   double acc = 0.0;
   for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) acc += partial[b];
@@ -738,7 +701,14 @@ __global__ __launch_bounds__(kThreads) void k_norm2_final(const double* __restri
 
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const T* __restrict__ w,
-                                                           const double* __restrict__ nrm, T* __restrict__ v) {
+                                                           const double* __restrict__ nrm, T* __restrict__ v,
+                                                           int64_t wstride, int64_t vstride,
+                                                           const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if (active && !active[z]) return;
+  w += z * wstride;
+  v += z * vstride;
+  nrm += z;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double a = nrm[0];
@@ -758,7 +728,15 @@ __global__ __launch_bounds__(kThreads) void k_scale_host(int64_t n, const Ti* __
 
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                      const double2* __restrict__ y, T* __restrict__ u) {
+                                                      const double2* __restrict__ y, T* __restrict__ u,
+                                                      int64_t vstride, int64_t ystride, int64_t ustride,
+                                                      const int* __restrict__ qs, const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if (active && !active[z]) return;
+  V += z * vstride;
+  y += z * ystride;
+  u += z * ustride;
+  if (qs) q = qs[z];
   __shared__ double2 ys[kMaxRestart + 1];
   if (threadIdx.x < q) ys[threadIdx.x] = y[threadIdx.x];
   __syncthreads();
@@ -771,9 +749,14 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, const T* __rest
 
 // x += z   (x FP64, z in storage type)
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restrict__ z, double2* __restrict__ x) {
+__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restrict__ zv, double2* __restrict__ x,
+                                                   int64_t zstride, int64_t xstride, const int* __restrict__ active) {
+  const int b = blockIdx.z;
+  if (active && !active[b]) return;
+  zv += b * zstride;
+  x += b * xstride;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = cadd(x[i], ld2(z[i]));
+  if (i < n) x[i] = cadd(x[i], ld2(zv[i]));
 }
 
 // w <- w - V h (FP64 arithmetic, stored in T) and rpart = per-block ||w||^2:
@@ -781,8 +764,15 @@ __global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restric
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_update_norm(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
                                                           const double2* __restrict__ h, T* __restrict__ w,
-                                                          double* __restrict__ rpart, const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+                                                          double* __restrict__ rpart, const int* __restrict__ flag,
+                                                          int64_t vstride, int64_t wstride, int64_t hstride,
+                                                          const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if ((active && !active[z]) || (flag && flag[z] == 0)) return;
+  V += z * vstride;
+  w += z * wstride;
+  h += z * hstride;
+  rpart += (int64_t)z * gridDim.x;
   __shared__ double2 hs[kMaxRestart + 1];
   __shared__ double sh[4];
   if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
@@ -812,7 +802,15 @@ __global__ __launch_bounds__(kThreads) void k_update_norm(int64_t n, const T* __
 // otherwise h2 = 0 and nrm = nrm1.  counter counts second passes.
 __global__ void k_reorth_decide(int q, const double2* __restrict__ h1, const double* __restrict__ nrm1,
                                 double2* __restrict__ h2, double* __restrict__ nrm, int* __restrict__ flag,
-                                int* __restrict__ counter) {
+                                int* __restrict__ counter, int64_t hstride, const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if (active && !active[z]) return;
+  h1 += z * hstride;
+  h2 += z * hstride;
+  nrm1 += z;
+  nrm += z;
+  flag += z;
+  counter += z;
   const int t = threadIdx.x;
   const double w0 = sqrt(h1[q].x);
   const int need = nrm1[0] < 0.70710678118654752 * w0 ? 1 : 0;
@@ -829,11 +827,10 @@ __global__ void k_reorth_decide(int q, const double2* __restrict__ h1, const dou
 // Column j of H (row-major, leading dimension m) = h1 + h2 with H(j+1, j) =
 // ||w||; applies the previous rotations, forms the new one, updates g and
 // writes est[j] = |g(j+1)| / bnorm.  At j = 0, g is reset to (beta, 0, ...).
-__global__ void k_givens(int j, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
+__device__ void givens_body(int j, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
                          const double* __restrict__ nrm, double2* __restrict__ H, double* __restrict__ cs,
                          double2* __restrict__ sn, double2* __restrict__ g, double beta, double bnorm,
                          double* __restrict__ est) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (j == 0) {
     for (int i = 0; i <= m; ++i) g[i] = make_double2(0.0, 0.0);
     g[0] = make_double2(beta, 0.0);
@@ -874,10 +871,30 @@ __global__ void k_givens(int j, int m, const double2* __restrict__ h1, const dou
   est[j] = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / bnorm;
 }
 
-// y = H(0:k,0:k)^-1 g(0:k) (upper triangular), one thread
-__global__ void k_backsolve(int k, int m, const double2* __restrict__ H, const double2* __restrict__ g,
-                            double2* __restrict__ y) {
+__global__ void k_givens(int j, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                         const double* __restrict__ nrm, double2* __restrict__ H, double* __restrict__ cs,
+                         double2* __restrict__ sn, double2* __restrict__ g, double beta, double bnorm,
+                         double* __restrict__ est) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  givens_body(j, m, h1, h2, nrm, H, cs, sn, g, beta, bnorm, est);
+}
+
+// One right-hand side per workgroup z; per-system arrays at fixed strides,
+// beta and bnorm from device arrays.
+__global__ void k_givens_b(int j, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                           const double* __restrict__ nrm, double2* __restrict__ H, double* __restrict__ cs,
+                           double2* __restrict__ sn, double2* __restrict__ g, const double* __restrict__ beta,
+                           const double* __restrict__ bnorm, double* __restrict__ est, int64_t hstride,
+                           const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if (threadIdx.x != 0 || (active && !active[z])) return;
+  givens_body(j, m, h1 + z * hstride, h2 + z * hstride, nrm + z, H + (int64_t)z * (m + 1) * m, cs + z * (m + 1),
+              sn + z * (m + 1), g + z * (m + 2), beta[z], bnorm[z], est + z * (m + 1));
+}
+
+// y = H(0:k,0:k)^-1 g(0:k) (upper triangular), one thread
+__device__ void backsolve_body(int k, int m, const double2* __restrict__ H, const double2* __restrict__ g,
+                            double2* __restrict__ y) {
   for (int i = k - 1; i >= 0; --i) {
     double2 acc = g[i];
     for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(H[i * m + l], y[l]));
@@ -885,6 +902,117 @@ __global__ void k_backsolve(int k, int m, const double2* __restrict__ H, const d
     const double den = d.x * d.x + d.y * d.y;
     y[i] = cmul(acc, make_double2(d.x / den, -d.y / den));
   }
+}
+
+__global__ void k_backsolve(int k, int m, const double2* __restrict__ H, const double2* __restrict__ g,
+                            double2* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  backsolve_body(k, m, H, g, y);
+}
+
+__global__ void k_backsolve_b(const int* __restrict__ ks, int m, const double2* __restrict__ H,
+                              const double2* __restrict__ g, double2* __restrict__ y, int64_t ystride,
+                              const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if (threadIdx.x != 0 || (active && !active[z])) return;
+  backsolve_body(ks[z], m, H + (int64_t)z * (m + 1) * m, g + z * (m + 2), y + z * ystride);
+}
+
+// ---- batched right-hand sides: the matrix / block inverses are read once
+// per launch for up to kBatchChunk systems (vectors of system r at r * ld).
+
+// z_r = Minv r_r for the active systems, one wavefront per block.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_block_apply_b(int64_t nb, const int* __restrict__ blk_ptr,
+                                                            const int* __restrict__ blk_dofs,
+                                                            const T* __restrict__ minv, int nrhs, int64_t rstride,
+                                                            const T* __restrict__ r, int64_t zstride,
+                                                            T* __restrict__ z, const int* __restrict__ active) {
+  __shared__ T rl[4][kBatchChunk][kMaxBlock];
+  const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + w;
+  int b0 = 0, sz = 0, dof = -1;
+  if (k < nb) {
+    b0 = blk_ptr[k];
+    sz = blk_ptr[k + 1] - b0;
+    if (i < sz) dof = blk_dofs[b0 + i];
+  }
+  const T* Mk = minv + k * kMaxBlock * kMaxBlock;
+  for (int c0 = 0; c0 < nrhs; c0 += kBatchChunk) {
+    const int cn = min(kBatchChunk, nrhs - c0);
+#pragma unroll
+    for (int q = 0; q < kBatchChunk; ++q) {
+      const bool on = q < cn && dof >= 0 && (!active || active[c0 + q]);
+      rl[w][q][i] = on ? r[(int64_t)(c0 + q) * rstride + dof] : zero2<T>();
+    }
+    __syncthreads();
+    if (dof >= 0) {
+      T acc[kBatchChunk];
+#pragma unroll
+      for (int q = 0; q < kBatchChunk; ++q) acc[q] = zero2<T>();
+      for (int j = 0; j < sz; ++j) {
+        const T mij = Mk[j * kMaxBlock + i];
+#pragma unroll
+        for (int q = 0; q < kBatchChunk; ++q)
+          if (q < cn) acc[q] = cfmaT(mij, rl[w][q][j], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < kBatchChunk; ++q)
+        if (q < cn && (!active || active[c0 + q])) z[(int64_t)(c0 + q) * zstride + dof] = acc[q];
+    }
+    __syncthreads();
+  }
+}
+
+// y_r = M~ x_r (penalty-free operator), or y_r = b_r - M~ x_r if b; 8 lanes per row.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_spmv_b(int64_t n, const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col, const T* __restrict__ val, int nrhs,
+                                                     int64_t ld, const T* __restrict__ x, const T* __restrict__ b,
+                                                     T* __restrict__ y, const int* __restrict__ active) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+  const int lane = threadIdx.x % kLanes;
+  for (int c0 = 0; c0 < nrhs; c0 += kBatchChunk) {
+    const int cn = min(kBatchChunk, nrhs - c0);
+    bool on[kBatchChunk];
+    T acc[kBatchChunk];
+#pragma unroll
+    for (int q = 0; q < kBatchChunk; ++q) {
+      on[q] = q < cn && (!active || active[c0 + q]);
+      acc[q] = zero2<T>();
+    }
+    if (row < n) {
+      for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) {
+        const T v = val[p];
+        const int c = col[p];
+#pragma unroll
+        for (int q = 0; q < kBatchChunk; ++q)
+          if (on[q]) acc[q] = cfmaT(v, x[(int64_t)(c0 + q) * ld + c], acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kBatchChunk; ++q)
+      for (int o = kLanes / 2; o > 0; o >>= 1) {
+        acc[q].x += __shfl_xor(acc[q].x, o, kLanes);
+        acc[q].y += __shfl_xor(acc[q].y, o, kLanes);
+      }
+    if (row < n && lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kBatchChunk; ++q)
+        if (on[q]) {
+          const int64_t o = (int64_t)(c0 + q) * ld + row;
+          y[o] = b ? st2<T>(csub(ld2(b[o]), ld2(acc[q]))) : acc[q];
+        }
+    }
+  }
+}
+
+// out_r = (T) in_r
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_convert_b(int64_t n, const double2* __restrict__ in, int64_t istride,
+                                                        T* __restrict__ out, int64_t ostride) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[blockIdx.z * ostride + i] = st2<T>(in[blockIdx.z * istride + i]);
 }
 
 // out = (complex64) in
@@ -896,7 +1024,9 @@ __global__ __launch_bounds__(kThreads) void k_to_c64(int64_t n, const double2* _
 
 __global__ __launch_bounds__(kThreads) void k_diag_scale(int64_t n, const double2* __restrict__ in,
                                                          const double* __restrict__ s, int divide,
-                                                         double2* __restrict__ out) {
+                                                         double2* __restrict__ out, int64_t istride, int64_t ostride) {
+  in += blockIdx.z * istride;
+  out += blockIdx.z * ostride;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double f = divide ? 1.0 / s[i] : s[i];
@@ -1031,14 +1161,14 @@ template <class T>
 void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2* partial, hipStream_t st,
                  int want_norm, const int* flag) {
   dim3 grid(mdot_parts(n), (q + 7) / 8);
-  k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial, want_norm, flag);
+  k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial, want_norm, flag, 0, 0, 0, nullptr);
 }
 void launch_reduce_cols(int q, int nparts, const double2* partial, double2* out, hipStream_t st, const int* flag) {
-  k_reduce_cols<<<q, kThreads, 0, st>>>(partial, nparts, out, flag);
+  k_reduce_cols<<<q, kThreads, 0, st>>>(partial, nparts, out, flag, 0, 0, nullptr);
 }
 void launch_reorth_decide(int q, const double2* h1, const double* nrm1, double2* h2, double* nrm, int* flag,
                           int* counter, hipStream_t st) {
-  k_reorth_decide<<<1, 64, 0, st>>>(q, h1, nrm1, h2, nrm, flag, counter);
+  k_reorth_decide<<<1, 64, 0, st>>>(q, h1, nrm1, h2, nrm, flag, counter, 0, nullptr);
 }
 template <class T>
 void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, hipStream_t st) {
@@ -1046,12 +1176,12 @@ void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, 
 }
 template <class T>
 void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipStream_t st) {
-  k_norm2_partial<T><<<kRedBlocks, kThreads, 0, st>>>(n, w, partial);
-  k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm, nullptr);
+  k_norm2_partial<T><<<kRedBlocks, kThreads, 0, st>>>(n, w, partial, 0, nullptr);
+  k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm, nullptr, nullptr);
 }
 template <class T>
 void launch_scale_by_inv(int64_t n, const T* w, const double* norm, T* v, hipStream_t st) {
-  k_scale_by_inv<T><<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v);
+  k_scale_by_inv<T><<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v, 0, 0, nullptr);
 }
 template <class Ti, class To>
 void launch_scale_host(int64_t n, const Ti* w, double a, To* v, hipStream_t st) {
@@ -1059,17 +1189,17 @@ void launch_scale_host(int64_t n, const Ti* w, double a, To* v, hipStream_t st) 
 }
 template <class T>
 void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y, T* u, hipStream_t st) {
-  k_combine<T><<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, y, u);
+  k_combine<T><<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, y, u, 0, 0, 0, nullptr, nullptr);
 }
 template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
-  k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x);
+  k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x, 0, 0, nullptr);
 }
 template <class T>
 void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
                         double* out_norm, hipStream_t st, const int* flag) {
-  k_update_norm<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart, flag);
-  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, flag);
+  k_update_norm<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart, flag, 0, 0, 0, nullptr);
+  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, flag, nullptr);
 }
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st) {
@@ -1077,6 +1207,92 @@ void launch_givens(int j, int m, const double2* h1, const double2* h2, const dou
 }
 void launch_backsolve(int k, int m, const double2* H, const double2* g, double2* y, hipStream_t st) {
   k_backsolve<<<1, 64, 0, st>>>(k, m, H, g, y);
+}
+// ---- batched launch wrappers (grid.z = system index)
+template <class T>
+void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, int nrhs,
+                          int64_t rstride, const T* r, int64_t zstride, T* z, const int* active, hipStream_t st) {
+  k_block_apply_b<T><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, nrhs, rstride, r, zstride,
+                                                              z, active);
+}
+template <class T>
+void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, int nrhs, int64_t ld, const T* x,
+                   const T* b, T* y, const int* active, hipStream_t st) {
+  k_spmv_b<T><<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, rowptr, col, val, nrhs, ld, x, b, y, active);
+}
+template <class T>
+void launch_mdot_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* w, int64_t wstride,
+                   double2* partial, int64_t pstride, int want_norm, const int* flag, const int* active, int nrhs,
+                   hipStream_t st) {
+  dim3 grid(mdot_parts(n), (q + 7) / 8, nrhs);
+  k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial, want_norm, flag, vstride, wstride, pstride, active);
+}
+void launch_reduce_cols_b(int q, int nparts, const double2* partial, int64_t pstride, double2* out, int64_t ostride,
+                          const int* flag, const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(q, 1, nrhs);
+  k_reduce_cols<<<grid, kThreads, 0, st>>>(partial, nparts, out, flag, pstride, ostride, active);
+}
+template <class T>
+void launch_update_norm_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* h,
+                          int64_t hstride, T* w, int64_t wstride, double* rpart, double* out_norm, const int* flag,
+                          const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(kRedBlocks, 1, nrhs);
+  k_update_norm<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart, flag, vstride, wstride, hstride, active);
+  dim3 g1(1, 1, nrhs);
+  k_norm2_final<<<g1, kThreads, 0, st>>>(rpart, out_norm, flag, active);
+}
+void launch_reorth_decide_b(int q, const double2* h1, int64_t hstride, const double* nrm1, double2* h2, double* nrm,
+                            int* flag, int* counter, const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(1, 1, nrhs);
+  k_reorth_decide<<<grid, 64, 0, st>>>(q, h1, nrm1, h2, nrm, flag, counter, hstride, active);
+}
+template <class T>
+void launch_norm2_b(int64_t n, const T* w, int64_t wstride, double* partial, double* out_norm, const int* active,
+                    int nrhs, hipStream_t st) {
+  dim3 grid(kRedBlocks, 1, nrhs);
+  k_norm2_partial<T><<<grid, kThreads, 0, st>>>(n, w, partial, wstride, active);
+  dim3 g1(1, 1, nrhs);
+  k_norm2_final<<<g1, kThreads, 0, st>>>(partial, out_norm, nullptr, active);
+}
+template <class T>
+void launch_scale_by_inv_b(int64_t n, const T* w, int64_t wstride, const double* norm, T* v, int64_t vstride,
+                           const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(blocks_for(n), 1, nrhs);
+  k_scale_by_inv<T><<<grid, kThreads, 0, st>>>(n, w, norm, v, wstride, vstride, active);
+}
+void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, const double* nrm,
+                     double2* H, double* cs, double2* sn, double2* g, const double* beta, const double* bnorm,
+                     double* est, const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(1, 1, nrhs);
+  k_givens_b<<<grid, 64, 0, st>>>(j, m, h1, h2, nrm, H, cs, sn, g, beta, bnorm, est, hstride, active);
+}
+void launch_backsolve_b(const int* ks, int m, const double2* H, const double2* g, double2* y, int64_t ystride,
+                        const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(1, 1, nrhs);
+  k_backsolve_b<<<grid, 64, 0, st>>>(ks, m, H, g, y, ystride, active);
+}
+template <class T>
+void launch_combine_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, const int* qs, const double2* y,
+                      int64_t ystride, T* u, int64_t ustride, const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(blocks_for(n), 1, nrhs);
+  k_combine<T><<<grid, kThreads, 0, st>>>(n, V, ldv, 0, y, u, vstride, ystride, ustride, qs, active);
+}
+template <class T>
+void launch_axpy_b(int64_t n, const T* z, int64_t zstride, double2* x, int64_t xstride, const int* active, int nrhs,
+                   hipStream_t st) {
+  dim3 grid(blocks_for(n), 1, nrhs);
+  k_axpy<T><<<grid, kThreads, 0, st>>>(n, z, x, zstride, xstride, active);
+}
+void launch_diag_scale_b(int64_t n, const double2* in, int64_t istride, const double* s, int divide, double2* out,
+                         int64_t ostride, int nrhs, hipStream_t st) {
+  dim3 grid(blocks_for(n), 1, nrhs);
+  k_diag_scale<<<grid, kThreads, 0, st>>>(n, in, s, divide, out, istride, ostride);
+}
+template <class T>
+void launch_to_storage_b(int64_t n, const double2* in, int64_t istride, T* out, int64_t ostride, int nrhs,
+                         hipStream_t st) {
+  dim3 grid(blocks_for(n), 1, nrhs);
+  k_convert_b<T><<<grid, kThreads, 0, st>>>(n, in, istride, out, ostride);
 }
 void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   k_to_c64<<<blocks_for(n), kThreads, 0, st>>>(n, in, out);
@@ -1097,8 +1313,27 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
 EDDY_INST(double2)
 EDDY_INST(float2)
 #undef EDDY_INST
+#define EDDY_INST_B(T)                                                                                            \
+  template void launch_block_apply_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, int64_t, \
+                                        T*, const int*, hipStream_t);                                             \
+  template void launch_spmv_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, const T*, T*,  \
+                                 const int*, hipStream_t);                                                        \
+  template void launch_mdot_b<T>(int64_t, const T*, int64_t, int64_t, int, const T*, int64_t, double2*, int64_t,   \
+                                 int, const int*, const int*, int, hipStream_t);                                  \
+  template void launch_update_norm_b<T>(int64_t, const T*, int64_t, int64_t, int, const double2*, int64_t, T*,     \
+                                        int64_t, double*, double*, const int*, const int*, int, hipStream_t);     \
+  template void launch_norm2_b<T>(int64_t, const T*, int64_t, double*, double*, const int*, int, hipStream_t);      \
+  template void launch_scale_by_inv_b<T>(int64_t, const T*, int64_t, const double*, T*, int64_t, const int*, int, \
+                                         hipStream_t);                                                            \
+  template void launch_combine_b<T>(int64_t, const T*, int64_t, int64_t, const int*, const double2*, int64_t, T*,  \
+                                    int64_t, const int*, int, hipStream_t);                                       \
+  template void launch_axpy_b<T>(int64_t, const T*, int64_t, double2*, int64_t, const int*, int, hipStream_t);      \
+  template void launch_to_storage_b<T>(int64_t, const double2*, int64_t, T*, int64_t, int, hipStream_t);
+EDDY_INST_B(double2)
+EDDY_INST_B(float2)
+#undef EDDY_INST_B
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st) {
-  k_diag_scale<<<blocks_for(n), kThreads, 0, st>>>(n, in, s, divide, out);
+  k_diag_scale<<<blocks_for(n), kThreads, 0, st>>>(n, in, s, divide, out, 0, 0);
 }
 void launch_zero(int64_t n, double2* x, hipStream_t st) { k_zero<<<blocks_for(n), kThreads, 0, st>>>(n, x); }
 void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, double2* V, double2* scratch,
@@ -1109,7 +1344,7 @@ void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, 
 }
 void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st) {
   k_udot_partial<<<kRedBlocks, kThreads, 0, st>>>(n, a, b, partial);
-  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, kRedBlocks, out, nullptr);
+  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, kRedBlocks, out, nullptr, 0, 0, nullptr);
 }
 void launch_edge_divergence(int64_t nv, const int* wtrowptr, const int* wtcol, const int* edges, const double2* b,
                             double2* d, hipStream_t st) {

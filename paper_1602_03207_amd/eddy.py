@@ -41,7 +41,7 @@ EXPORTS = [
     "eddy_mesh_create", "eddy_mesh_destroy", "eddy_mesh_counts", "eddy_mesh_edges",
     "eddy_mesh_conductor_nodes", "eddy_mesh_blocks", "eddy_op_workspace_bytes", "eddy_op_create",
     "eddy_op_destroy", "eddy_op_assemble", "eddy_rhs_from_current", "eddy_solve_workspace_bytes",
-    "eddy_solve", "eddy_impedance", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile",
+    "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched", "eddy_impedance", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile",
     "eddy_status_string", "eddy_last_error",
 ]
 
@@ -65,6 +65,8 @@ def _load():
         "eddy_rhs_from_current": [VP, VP, VP, VP],
         "eddy_solve_workspace_bytes": [VP, P(_Opts), P(C.c_size_t)],
         "eddy_solve": [VP, VP, VP, P(_Opts), VP, C.c_size_t, P(_Report), VP],
+        "eddy_solve_batched_workspace_bytes": [VP, I32, P(_Opts), P(C.c_size_t)],
+        "eddy_solve_batched": [VP, I32, VP, VP, P(_Opts), VP, C.c_size_t, P(_Report), VP],
         "eddy_impedance": [VP, I32, VP, I32, VP, P(D), P(D), VP],
         "eddy_edge_field": [VP, VP, VP, VP],
         "eddy_spmv": [VP, VP, VP, VP],
@@ -245,6 +247,27 @@ class Operator:
         return x, SolveReport(rep.iters, rep.restarts, bool(rep.converged), bool(rep.breakdown), rep.relres,
                               rep.est_relres, rep.seconds, bool(rep.gauge_in_operator), rep.cg_iters,
                               rep.div_residual, rep.precision_used, rep.reorth_steps)
+
+    def solve_batched(self, B, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64"):
+        """B: complex128 device tensor [nrhs, ndof] -> (X [nrhs, ndof], [SolveReport])."""
+        import torch
+        B = B.reshape(-1, self.ndof).contiguous()
+        nrhs = B.shape[0]
+        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1}[precision])
+        nbytes = C.c_size_t()
+        _check(_lib.eddy_solve_batched_workspace_bytes(self._h, nrhs, C.byref(opts), C.byref(nbytes)),
+               "eddy_solve_batched_workspace_bytes")
+        key = ("batch", nbytes.value)
+        if getattr(self, "_batch_ws", None) is None or self._batch_ws[2] < nbytes.value:
+            buf, p = _aligned(nbytes.value, self.device)
+            self._batch_ws = (buf, p, nbytes.value)
+        X = torch.empty_like(B) if out is None else out
+        reps = (_Report * nrhs)()
+        _check(_lib.eddy_solve_batched(self._h, nrhs, _dev(B), _dev(X), C.byref(opts), self._batch_ws[1],
+                                       self._batch_ws[2], reps, _stream()), "eddy_solve_batched")
+        return X, [SolveReport(r.iters, r.restarts, bool(r.converged), bool(r.breakdown), r.relres, r.est_relres,
+                               r.seconds, bool(r.gauge_in_operator), r.cg_iters, r.div_residual, r.precision_used,
+                               r.reorth_steps) for r in reps]
 
     def spmv(self, x, out=None):
         y = self._c128() if out is None else out

@@ -173,3 +173,17 @@ def test_fullsize_solves_fp64_and_mixed():
     assert abs(Z[0, 0] - Z64[0, 0]) <= 1e-6 * abs(Z64[0, 0])
     assert abs(Z[0, 1] - Z[1, 0]) <= 1e-6 * abs(Z[0, 1])
     assert Z[0, 0].real > 0 and Z[1, 1].real > 0 and Z[0, 0].imag < 0
+
+
+def test_fullsize_batched_scan_matches_single():
+    """Four probe positions of a scan solved together equal separate solves."""
+    S = full()
+    op, m = S["op"], S["m"]
+    zs = [-6e-3, -2e-3, 2e-3, 6e-3]
+    B = torch.stack([op.rhs_from_current(torch.from_numpy(probe_currents(m, z)[0]).cuda()) for z in zs])
+    X, reps = op.solve_batched(B, tol=1e-8, restart=48, max_iter=20000, precision="mixed")
+    assert all(r.converged for r in reps)
+    x1, r1 = op.solve(B[1].clone(), tol=1e-8, restart=48, max_iter=20000, precision="mixed")
+    assert abs(reps[1].iters - r1.iters) <= 1
+    assert (torch.linalg.norm(X[1] - x1) / torch.linalg.norm(x1)).item() <= 1e-7
+    print("batched iters", [r.iters for r in reps], f"batch {reps[0].seconds:.2f} s vs single {r1.seconds:.2f} s")

@@ -265,3 +265,35 @@ def test_tau_precond_changes_only_the_preconditioner():
     _, res = solve_gmres(s, m.xyz, s.rhs(J), block=64, m=30, tol=1e-10, tau_precond=0.1)
     _, rep10 = op2.solve(b, tol=1e-10)
     assert abs(rep10.iters - res.iters) <= max(2, 0.05 * res.iters)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_solve_matches_single_solves(precision):
+    """The batched solver runs the same GMRES per system: same iterations and
+    the same solution as separate solves (and the oracle's direct solve)."""
+    from oracle.solve import direct
+    from oracle.post import remove_v_mean
+    m, s, op, _ = case("c1")
+    Js = [cube_current(m, seed) for seed in (0, 1, 2)]
+    B = torch.stack([op.rhs_from_current(torch.from_numpy(J).cuda()) for J in Js])
+    X, reps = op.solve_batched(B, tol=1e-11, restart=30, max_iter=3000, precision=precision)
+    for r, J in enumerate(Js):
+        x1, rep1 = op.solve(B[r].clone(), tol=1e-11, restart=30, max_iter=3000, precision=precision)
+        assert reps[r].converged and reps[r].relres <= 1e-11
+        assert abs(reps[r].iters - rep1.iters) <= 1, (reps[r].iters, rep1.iters)
+        assert torch.linalg.norm(X[r] - x1).item() <= 1e-9 * torch.linalg.norm(x1).item()
+        xo = remove_v_mean(s, direct(s, s.rhs(J)))
+        assert np.linalg.norm(X[r].cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
+def test_batched_solve_rejects_non_solenoidal_and_handles_zero_rhs():
+    from paper_1602_03207_amd import eddy
+    m, s, op, J = case("c1")
+    b = op.rhs_from_current(torch.from_numpy(J).cuda())
+    Z = torch.stack([b, torch.zeros_like(b)])
+    X, reps = op.solve_batched(Z, tol=1e-10)
+    assert reps[0].converged and reps[1].converged and torch.count_nonzero(X[1]) == 0
+    Jr = np.random.default_rng(3).normal(size=(m.nt, 3))
+    bad = torch.stack([b, op.rhs_from_current(torch.from_numpy(Jr).cuda())])
+    with pytest.raises(eddy.EddyError, match="divergence-free"):
+        op.solve_batched(bad, tol=1e-10)
