@@ -192,6 +192,36 @@ eddy_status eddy_impedance(const eddy_op* op, int32_t nsol, const eddy_c128* x_d
  * the edge degrees of freedom of E = i omega A + grad V (Eq. 2). */
 eddy_status eddy_edge_field(const eddy_op* op, const eddy_c128* x_dev, eddy_c128* E_dev, eddy_stream stream);
 
+/* Impedance change caused by a defect, as a volume integral over the defect
+ * region (Section 2, Eq. 12, with the vacuum taken as sigma = 0): for two
+ * operators assembled on the same geometry (xyz, tet, region; checked through
+ * a hash taken at eddy_mesh_create, else EDDY_ERR_MESH) and the same omega,
+ * `op_defect` with the defect's (nu, sigma) and `op_free` without it,
+ *   dZ[k*nl + l] = (1 / (I_k I_l)) * sum over tetrahedra where (nu, sigma)
+ *     differ of [ i omega dnu int curl A_k . curl A0_l - dsig int E_k . E0_l ],
+ * dnu, dsig = defect minus free values, E = i omega A + grad V (Eq. 2),
+ * x_defect[nk][ndof(op_defect)] the defect solutions, x_free[nl][ndof(op_free)]
+ * the defect-free ones (device, complex128), currents_k[nk], currents_l[nl]
+ * (host, A), dZ[nk][nl] host.  V of x_free is taken as 0 at nodes that are not
+ * conductor nodes of op_free.  For Galerkin solutions of the two systems this
+ * equals Z_defect - Z_free of eddy_impedance exactly (up to solver tolerance),
+ * without the cancellation of subtracting two nearly equal impedances.
+ * Synchronises `stream`. */
+eddy_status eddy_delta_z_volume(const eddy_op* op_defect, int32_t nk, const eddy_c128* x_defect,
+                                const eddy_op* op_free, int32_t nl, const eddy_c128* x_free,
+                                const double* currents_k, const double* currents_l, eddy_c128* dZ_host,
+                                eddy_stream stream);
+
+/* Eddy-current testing signals (Section 2, Eq. 11) for npos probe positions:
+ * dZ = Z_defect - Z_free (the impedance change the defect causes), then
+ * Z_FA = (i/2)(dZ11 + dZ12) (absolute mode) and Z_F3 = (i/2)(dZ11 - dZ22)
+ * (differential mode).  Z_defect, Z_free, dZ: [npos][2][2] row-major
+ * (Z[p*4 + k*2 + l] = Z_kl, coil k measuring the field of coil l); Z_FA and
+ * Z_F3: [npos].  All host arrays; dZ may be NULL.  Z_free = NULL: Z_defect
+ * already holds dZ (e.g. from eddy_delta_z_volume). */
+eddy_status eddy_ect_signals(int32_t npos, const eddy_c128* Z_defect, const eddy_c128* Z_free, eddy_c128* dZ,
+                             eddy_c128* Z_FA, eddy_c128* Z_F3);
+
 /* ---- building blocks (parity tests and benchmarks) ---------------------
  * y = M x with the gauge applied in factored form (unscaled system). */
 eddy_status eddy_spmv(const eddy_op* op, const eddy_c128* x_dev, eddy_c128* y_dev, eddy_stream stream);

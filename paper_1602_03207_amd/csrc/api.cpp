@@ -2,6 +2,7 @@
 // assembly sequence, the GMRES driver and the output calls.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -55,11 +56,12 @@ using namespace eddy;
 struct eddy_op {
   int64_t nv, nt, ne, nc, nct, n, nnz, nnzw, nb;
   int32_t nreg, ncomp, bsize;
+  uint64_t geom_hash;
   double tau, tau_p, delta_v, omega = 0;
   bool assembled = false;
   // static (uploaded at create)
   double* xyz;
-  int *tet, *region, *cidx, *edge_v, *comp, *edges, *cond_nodes;
+  int *tet, *region, *cidx, *edge_v, *comp, *edges, *cond_nodes, *tet2edge, *vmap;
   std::vector<int32_t> is_cond;
   uint8_t* signbits;
   int *rowptr, *col, *diagpos, *cptr, *clist;
@@ -100,6 +102,8 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->comp = c.take<int>(m->nc);
   o->edges = c.take<int>(m->ne * 2);
   o->cond_nodes = c.take<int>(m->nc);
+  o->tet2edge = c.take<int>(m->nt * 6);
+  o->vmap = c.take<int>(m->nv);
   o->rowptr = c.take<int>(m->ndof() + 1);
   o->col = c.take<int>(m->nnz());
   o->diagpos = c.take<int>(m->ndof());
@@ -148,6 +152,18 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->rred = c.take<double>(kRedBlocks + 8);
   o->status = c.take<int>(4);
   return c.off + 256;
+}
+
+uint64_t geometry_hash(const eddy_mesh* m) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  };
+  mix(m->xyz.data(), sizeof(double) * m->xyz.size());
+  mix(m->tet.data(), sizeof(int32_t) * m->tet.size());
+  mix(m->region.data(), sizeof(int32_t) * m->region.size());
+  return h;
 }
 
 eddy_status check_params(const eddy_params* p) {
@@ -212,6 +228,7 @@ eddy_status eddy_mesh_create(int64_t nv, const double* xyz, int64_t nt, const in
     m->tet.assign(tet, tet + nt * 4);
     m->region.assign(region, region + nt);
     m->is_cond.assign(is_conductor, is_conductor + nreg);
+    m->geom_hash = geometry_hash(m);
     eddy_status st = build_mesh(m);
     if (st != EDDY_OK) { delete m; return st; }
   } catch (const std::exception& e) {
@@ -296,6 +313,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   o->nv = m->nv; o->nt = m->nt; o->ne = m->ne; o->nc = m->nc; o->nct = m->nct; o->n = m->ndof();
   o->nnz = m->nnz(); o->nnzw = m->nnzw(); o->nb = (int64_t)m->blk_ptr.size() - 1;
   o->nreg = m->nreg; o->ncomp = m->ncomp; o->bsize = p->block_size;
+  o->geom_hash = m->geom_hash;
   o->tau = p->tau_gauge; o->delta_v = p->delta_v;
   o->tau_p = p->tau_precond > 0 ? p->tau_precond : p->tau_gauge;
   o->is_cond = m->is_cond;
@@ -310,7 +328,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
 #define UP(dst, src) if (r == EDDY_OK) r = upload(dst, src, s)
   UP(o->xyz, m->xyz); UP(o->tet, m->tet); UP(o->region, m->region); UP(o->cidx, m->cidx);
   UP(o->signbits, m->signbits); UP(o->edge_v, m->edge_v); UP(o->comp, m->comp);
-  UP(o->edges, m->edges); UP(o->cond_nodes, m->cond_nodes);
+  UP(o->edges, m->edges); UP(o->cond_nodes, m->cond_nodes); UP(o->tet2edge, m->tet2edge); UP(o->vmap, m->vmap);
   UP(o->rowptr, m->rowptr); UP(o->col, m->col); UP(o->diagpos, m->diagpos); UP(o->cptr, m->cptr);
   UP(o->clist, m->clist); UP(o->wrowptr, m->wrowptr); UP(o->wcol, m->wcol); UP(o->wcptr, m->wcptr);
   UP(o->wclist, m->wclist); UP(o->wtrowptr, m->wtrowptr); UP(o->wtcol, m->wtcol); UP(o->wtperm, m->wtperm);
@@ -1073,6 +1091,67 @@ eddy_status eddy_impedance(const eddy_op* o, int32_t nsol, const eddy_c128* x_de
       Z[k * nsrc + l].re = z.real();
       Z[k * nsrc + l].im = z.imag();
     }
+  return EDDY_OK;
+}
+
+eddy_status eddy_delta_z_volume(const eddy_op* od, int32_t nk, const eddy_c128* xd, const eddy_op* o0, int32_t nl,
+                                const eddy_c128* x0, const double* cur_k, const double* cur_l, eddy_c128* dZ,
+                                eddy_stream stream) {
+  if (!od || !o0 || !xd || !x0 || !cur_k || !cur_l || !dZ || nk < 1 || nl < 1) {
+    set_error("bad argument (NULL pointer or nk, nl < 1)");
+    return EDDY_ERR_ARG;
+  }
+  if (!od->assembled || !o0->assembled) { set_error("operators not assembled"); return EDDY_ERR_ARG; }
+  if (od->geom_hash != o0->geom_hash || od->nt != o0->nt || od->nv != o0->nv || od->ne != o0->ne ||
+      od->nreg != o0->nreg) {
+    set_error("the two operators are not built on the same geometry (xyz, tet, region)");
+    return EDDY_ERR_MESH;
+  }
+  if (std::abs(od->omega - o0->omega) > 1e-14 * od->omega) { set_error("the two operators differ in omega"); return EDDY_ERR_ARG; }
+  for (int k = 0; k < nk; ++k)
+    if (!(cur_k[k] != 0)) { set_error("currents must be nonzero"); return EDDY_ERR_ARG; }
+  for (int l = 0; l < nl; ++l)
+    if (!(cur_l[l] != 0)) { set_error("currents must be nonzero"); return EDDY_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nout = (int64_t)nk * nl;
+  if (nout > od->n) { set_error("nk * nl exceeds the operator's scratch"); return EDDY_ERR_ARG; }
+  for (int k = 0; k < nk; ++k)
+    for (int l0 = 0; l0 < nl; l0 += kMaxDzCols) {
+      const int q = std::min(kMaxDzCols, nl - l0);
+      launch_dz_volume(od->nt, od->xyz, od->tet, od->region, od->signbits, od->tet2edge, od->nu_reg, od->sig_reg,
+                       o0->nu_reg, o0->sig_reg, od->omega, od->ne, (const double2*)xd + (int64_t)k * od->n, od->vmap,
+                       q, (const double2*)x0 + (int64_t)l0 * o0->n, o0->n, o0->vmap, od->red,
+                       od->tmp1 + (int64_t)k * nl + l0, s);
+    }
+  HIP_TRY(hipGetLastError());
+  std::vector<double2> acc((size_t)nout);
+  HIP_TRY(hipMemcpyAsync(acc.data(), od->tmp1, sizeof(double2) * nout, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < nk; ++k)
+    for (int l = 0; l < nl; ++l) {
+      const double2 a = acc[(size_t)k * nl + l];
+      dZ[k * nl + l] = {a.x / (cur_k[k] * cur_l[l]), a.y / (cur_k[k] * cur_l[l])};
+    }
+  return EDDY_OK;
+}
+
+eddy_status eddy_ect_signals(int32_t npos, const eddy_c128* Zd, const eddy_c128* Z0, eddy_c128* dZ,
+                             eddy_c128* Z_FA, eddy_c128* Z_F3) {
+  if (npos < 0 || (npos > 0 && (!Zd || !Z_FA || !Z_F3))) { set_error("bad argument"); return EDDY_ERR_ARG; }
+  using cd = std::complex<double>;
+  const cd half_i(0.0, 0.5);
+  for (int32_t p = 0; p < npos; ++p) {
+    cd d[4];
+    for (int k = 0; k < 4; ++k) {
+      d[k] = cd(Zd[4 * p + k].re, Zd[4 * p + k].im);
+      if (Z0) d[k] -= cd(Z0[4 * p + k].re, Z0[4 * p + k].im);
+      if (dZ) dZ[4 * p + k] = {d[k].real(), d[k].imag()};
+    }
+    const cd fa = half_i * (d[0] + d[1]);   // (i/2)(dZ11 + dZ12)
+    const cd f3 = half_i * (d[0] - d[3]);   // (i/2)(dZ11 - dZ22)
+    Z_FA[p] = {fa.real(), fa.imag()};
+    Z_F3[p] = {f3.real(), f3.imag()};
+  }
   return EDDY_OK;
 }
 

@@ -26,8 +26,9 @@ namespace eddy {
 constexpr int kLocalEdge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 constexpr int kMaxBlock = 64;       // block-Jacobi block size limit (LDS-resident inverse)
 constexpr int kMaxRestart = 64;
-constexpr int kMaxWRow = 32;
-constexpr int kBatchChunk = 8;     // systems per pass of the batched SpMV / block-Jacobi kernels       // max nodes adjacent to one edge (LDS-staged gauge blocks)
+constexpr int kMaxWRow = 32;       // max nodes adjacent to one edge (LDS-staged gauge blocks)
+constexpr int kBatchChunk = 8;     // systems per pass of the batched SpMV / block-Jacobi kernels
+constexpr int kMaxDzCols = 4;      // free-configuration solutions per pass of the defect-volume kernel
 
 inline int pair6(int l, int m) {    // upper-triangle slot of a symmetric 6x6
   if (l > m) { int t = l; l = m; m = t; }
@@ -49,6 +50,7 @@ struct eddy_mesh {
   std::vector<int32_t> tet;         // nt*4
   std::vector<int32_t> region;      // nt
   std::vector<int32_t> is_cond;     // nreg
+  uint64_t geom_hash = 0;           // FNV-1a over xyz, tet and region (same geometry <=> same hash)
   // topology
   int64_t ne = 0, nc = 0, nct = 0;
   int32_t ncomp = 0;

@@ -139,6 +139,14 @@ void launch_cg_dir(int64_t n, const double2* rz_new, const double2* rz_old, cons
                    hipStream_t st);
 void launch_project(int64_t ne, int64_t nc, const int* edges, const int* cond_nodes, const double2* psi, double omega,
                     double2* x, hipStream_t st);
+// Defect-region volume form of the impedance change for one defect-configuration
+// solution xd against nl <= kMaxDzCols free-configuration solutions (x0 + l*ld0);
+// out[l] = sum over tetrahedra of i w dnu |K| curl A_d . curl A_0 - dsig int E_d . E_0.
+void launch_dz_volume(int64_t nt, const double* xyz, const int* tet, const int* region, const uint8_t* signbits,
+                      const int* tet2edge, const double* nu_d, const double* sig_d, const double* nu_0,
+                      const double* sig_0, double omega, int64_t ne, const double2* xd, const int* vmap_d, int nl,
+                      const double2* x0, int64_t ld0, const int* vmap_0, double2* partial, double2* out,
+                      hipStream_t st);
 void launch_edge_field(int64_t ne, const int* edge_v, const double2* x, double omega, double2* E, hipStream_t st);
 
 }  // namespace eddy

@@ -1078,6 +1078,139 @@ __global__ __launch_bounds__(kThreads) void k_udot_partial(int64_t n, const doub
   if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(re, im);
 }
 
+// Per-tetrahedron fields of one solution x = (A, V) of a configuration whose
+// conductor-node numbering is vmap (-1: no V there, taken as 0).  The lowest-
+// order edge field E_h = i w A_h + grad V_h on K is sum_a lambda_a u_a with
+// u_a = sum_b c_ab grad(lambda_b), c_ab = -c_ba the local edge coefficient of
+// the edge (a, b) (Whitney functions lambda_a grad lambda_b - lambda_b grad
+// lambda_a); grad V_h lies in the same space with c_ab = V_b - V_a.  curl A_h
+// = sum 2 A_ab grad(lambda_a) x grad(lambda_b).
+__device__ __forceinline__ void tet_fields(const double g[4][3], const int e6[6], double sg[6], const int n4[4],
+                                           const double2* __restrict__ x, int64_t ne, const int* __restrict__ vmap,
+                                           double omega, double2 u[4][3], double2 cu[3]) {
+  constexpr int ea[6] = {0, 0, 0, 1, 1, 2};
+  constexpr int eb[6] = {1, 2, 3, 2, 3, 3};
+  double2 v[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int c = vmap[n4[a]];
+    v[a] = c >= 0 ? x[ne + c] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) u[a][j] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) cu[j] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    const int a = ea[l], b = eb[l];
+    const double2 A = x[e6[l]];
+    const double2 Al = make_double2(sg[l] * A.x, sg[l] * A.y);          // local-orientation A
+    // c_ab = i w A_ab + V_b - V_a
+    const double2 c = make_double2(-omega * Al.y + v[b].x - v[a].x, omega * Al.x + v[b].y - v[a].y);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      u[a][j] = rfma(g[b][j], c, u[a][j]);
+      u[b][j] = rfma(-g[a][j], c, u[b][j]);
+    }
+    const double cx = g[a][1] * g[b][2] - g[a][2] * g[b][1];
+    const double cy = g[a][2] * g[b][0] - g[a][0] * g[b][2];
+    const double cz = g[a][0] * g[b][1] - g[a][1] * g[b][0];
+    cu[0] = rfma(2.0 * cx, Al, cu[0]);
+    cu[1] = rfma(2.0 * cy, Al, cu[1]);
+    cu[2] = rfma(2.0 * cz, Al, cu[2]);
+  }
+}
+
+// out[l] partials: sum over tetrahedra whose (nu, sigma) differ between the
+// two configurations of  i w dnu |K| curl A_d . curl A_0  -  dsig int_K E_d . E_0,
+// with int_K lambda_a lambda_b = |K| (1 + delta_ab) / 20.  Grid-stride over
+// tetrahedra; most of them are skipped after reading their region.
+__global__ __launch_bounds__(kThreads) void k_dz_volume(
+    int64_t nt, const double* __restrict__ xyz, const int* __restrict__ tet, const int* __restrict__ region,
+    const uint8_t* __restrict__ signbits, const int* __restrict__ tet2edge, const double* __restrict__ nu_d,
+    const double* __restrict__ sig_d, const double* __restrict__ nu_0, const double* __restrict__ sig_0, double omega,
+    int64_t ne, const double2* __restrict__ xd, const int* __restrict__ vmap_d, int nl, const double2* __restrict__ x0,
+    int64_t ld0, const int* __restrict__ vmap_0, double2* __restrict__ partial) {
+  __shared__ double sh[4];
+  double2 acc[kMaxDzCols];
+#pragma unroll
+  for (int l = 0; l < kMaxDzCols; ++l) acc[l] = make_double2(0.0, 0.0);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+    const int r = region[t];
+    const double dnu = nu_d[r] - nu_0[r], dsig = sig_d[r] - sig_0[r];
+    if (dnu == 0.0 && dsig == 0.0) continue;
+    const int4 nd = reinterpret_cast<const int4*>(tet)[t];
+    const int n4[4] = {nd.x, nd.y, nd.z, nd.w};
+    double p[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) p[k][j] = xyz[3 * (int64_t)n4[k] + j];
+    double e1[3], e2[3], e3[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      e1[j] = p[1][j] - p[0][j];
+      e2[j] = p[2][j] - p[0][j];
+      e3[j] = p[3][j] - p[0][j];
+    }
+    const double c23[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2], e2[0] * e3[1] - e2[1] * e3[0]};
+    const double c31[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2], e3[0] * e1[1] - e3[1] * e1[0]};
+    const double c12[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
+    const double id = 1.0 / det;
+    const double vol = fabs(det) * (1.0 / 6.0);
+    double g[4][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      g[1][j] = c23[j] * id;
+      g[2][j] = c31[j] * id;
+      g[3][j] = c12[j] * id;
+      g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
+    }
+    int e6[6];
+    double sg[6];
+    const uint8_t sb = signbits[t];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      e6[l] = tet2edge[6 * t + l];
+      sg[l] = ((sb >> l) & 1) ? -1.0 : 1.0;
+    }
+    double2 ud[4][3], cd[3];
+    tet_fields(g, e6, sg, n4, xd, ne, vmap_d, omega, ud, cd);
+    double2 sd[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sd[j] = cadd(cadd(ud[0][j], ud[1][j]), cadd(ud[2][j], ud[3][j]));
+#pragma unroll
+    for (int l = 0; l < kMaxDzCols; ++l) {
+      if (l >= nl) break;
+      double2 u0[4][3], c0[3];
+      tet_fields(g, e6, sg, n4, x0 + (int64_t)l * ld0, ne, vmap_0, omega, u0, c0);
+      double2 ee = make_double2(0.0, 0.0), cc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double2 s0 = cadd(cadd(u0[0][j], u0[1][j]), cadd(u0[2][j], u0[3][j]));
+        ee = cfma(sd[j], s0, ee);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ee = cfma(ud[a][j], u0[a][j], ee);
+        cc = cfma(cd[j], c0[j], cc);
+      }
+      // i w dnu |K| cc - dsig |K|/20 ee
+      const double fe = -dsig * vol * (1.0 / 20.0), fc = omega * dnu * vol;
+      acc[l].x += fe * ee.x - fc * cc.y;
+      acc[l].y += fe * ee.y + fc * cc.x;
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < kMaxDzCols; ++l) {
+    if (l >= nl) break;
+    const double re = block_sum(acc[l].x, sh);
+    const double im = block_sum(acc[l].y, sh);
+    if (threadIdx.x == 0) partial[(int64_t)l * gridDim.x + blockIdx.x] = make_double2(re, im);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_edge_field(int64_t ne, const int* __restrict__ edge_v,
                                                          const double2* __restrict__ x, double omega,
                                                          double2* __restrict__ E) {
@@ -1341,6 +1474,15 @@ void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, 
   if (ncomp <= 0 || nc <= 0) return;
   k_vmean<<<ncomp, kThreads, 0, st>>>(nc, comp, lumped, V, scratch);
   k_vmean_sub<<<blocks_for(nc), kThreads, 0, st>>>(nc, comp, scratch, V);
+}
+void launch_dz_volume(int64_t nt, const double* xyz, const int* tet, const int* region, const uint8_t* signbits,
+                      const int* tet2edge, const double* nu_d, const double* sig_d, const double* nu_0,
+                      const double* sig_0, double omega, int64_t ne, const double2* xd, const int* vmap_d, int nl,
+                      const double2* x0, int64_t ld0, const int* vmap_0, double2* partial, double2* out,
+                      hipStream_t st) {
+  k_dz_volume<<<kRedBlocks, kThreads, 0, st>>>(nt, xyz, tet, region, signbits, tet2edge, nu_d, sig_d, nu_0, sig_0,
+                                               omega, ne, xd, vmap_d, nl, x0, ld0, vmap_0, partial);
+  k_reduce_cols<<<nl, kThreads, 0, st>>>(partial, kRedBlocks, out, nullptr, 0, 0, nullptr);
 }
 void launch_udot(int64_t n, const double2* a, const double2* b, double2* partial, double2* out, hipStream_t st) {
   k_udot_partial<<<kRedBlocks, kThreads, 0, st>>>(n, a, b, partial);

@@ -41,7 +41,8 @@ EXPORTS = [
     "eddy_mesh_create", "eddy_mesh_destroy", "eddy_mesh_counts", "eddy_mesh_edges",
     "eddy_mesh_conductor_nodes", "eddy_mesh_blocks", "eddy_op_workspace_bytes", "eddy_op_create",
     "eddy_op_destroy", "eddy_op_assemble", "eddy_rhs_from_current", "eddy_solve_workspace_bytes",
-    "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched", "eddy_impedance", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile",
+    "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched", "eddy_impedance", "eddy_delta_z_volume",
+    "eddy_ect_signals", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile",
     "eddy_status_string", "eddy_last_error",
 ]
 
@@ -68,6 +69,8 @@ def _load():
         "eddy_solve_batched_workspace_bytes": [VP, I32, P(_Opts), P(C.c_size_t)],
         "eddy_solve_batched": [VP, I32, VP, VP, P(_Opts), VP, C.c_size_t, P(_Report), VP],
         "eddy_impedance": [VP, I32, VP, I32, VP, P(D), P(D), VP],
+        "eddy_delta_z_volume": [VP, I32, VP, VP, I32, VP, P(D), P(D), P(D), VP],
+        "eddy_ect_signals": [I32, P(D), P(D), P(D), P(D), P(D)],
         "eddy_edge_field": [VP, VP, VP, VP],
         "eddy_spmv": [VP, VP, VP, VP],
         "eddy_precond_apply": [VP, VP, VP, VP],
@@ -108,6 +111,45 @@ def _stream():
 
 def _dev(t):
     return C.c_void_p(t.data_ptr())
+
+
+def ect_signals(Z_defect, Z_free=None):
+    """(dZ [npos,2,2], Z_FA [npos], Z_F3 [npos]) from per-position 2x2 coil impedance
+    matrices with and without the defect (eddy_ect_signals); Z_free=None takes
+    Z_defect as the change dZ itself."""
+    Zd = np.ascontiguousarray(np.asarray(Z_defect, dtype=np.complex128).reshape(-1, 2, 2))
+    Z0 = None
+    if Z_free is not None:
+        Z0 = np.ascontiguousarray(np.asarray(Z_free, dtype=np.complex128).reshape(-1, 2, 2))
+        if Zd.shape != Z0.shape:
+            raise ValueError("Z_defect and Z_free shapes differ")
+    npos = Zd.shape[0]
+    dZ = np.empty_like(Zd)
+    fa = np.empty(npos, np.complex128)
+    f3 = np.empty(npos, np.complex128)
+    D = C.POINTER(C.c_double)
+    _check(_lib.eddy_ect_signals(npos, Zd.ctypes.data_as(D), None if Z0 is None else Z0.ctypes.data_as(D),
+                                 dZ.ctypes.data_as(D), fa.ctypes.data_as(D), f3.ctypes.data_as(D)),
+           "eddy_ect_signals")
+    return dZ, fa, f3
+
+
+def delta_z_volume(op_defect, x_defect, op_free, x_free, currents_k, currents_l):
+    """dZ[k, l] as the defect-region volume integral (eddy_delta_z_volume).
+
+    x_defect: [nk, op_defect.ndof], x_free: [nl, op_free.ndof] complex128 device
+    solutions of the two configurations on one geometry."""
+    xd = x_defect.reshape(-1, op_defect.ndof).contiguous()
+    x0 = x_free.reshape(-1, op_free.ndof).contiguous()
+    ck = np.ascontiguousarray(currents_k, dtype=np.float64)
+    cl = np.ascontiguousarray(currents_l, dtype=np.float64)
+    if ck.size != xd.shape[0] or cl.size != x0.shape[0]:
+        raise ValueError("one current per solution")
+    dZ = np.empty((xd.shape[0], x0.shape[0]), np.complex128)
+    _check(_lib.eddy_delta_z_volume(op_defect._h, xd.shape[0], _dev(xd), op_free._h, x0.shape[0], _dev(x0),
+                                    _ptr(ck, C.c_double), _ptr(cl, C.c_double),
+                                    dZ.ctypes.data_as(C.POINTER(C.c_double)), _stream()), "eddy_delta_z_volume")
+    return dZ
 
 
 class Mesh:

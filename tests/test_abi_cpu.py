@@ -93,3 +93,20 @@ def test_either_tet_orientation_accepted():
     M1 = eddy.Mesh(m.xyz, m.tet, m.region, [0, 1])
     M2 = eddy.Mesh(m.xyz, tet, m.region, [0, 1])
     assert np.array_equal(M1.edges(), M2.edges()) and M1.nnz == M2.nnz
+
+
+def test_ect_signals_host_call_matches_oracle():
+    """eddy_ect_signals runs on the host: Eq. 11 against the oracle on seeded
+    values, with and without the defect-free matrices."""
+    from oracle.post import ect_signals as oracle_signals
+    eddy = lib()
+    rng = np.random.default_rng(5)
+    Zd = rng.normal(size=(7, 2, 2)) + 1j * rng.normal(size=(7, 2, 2))
+    Z0 = rng.normal(size=(7, 2, 2)) + 1j * rng.normal(size=(7, 2, 2))
+    dZ, fa, f3 = eddy.ect_signals(Zd, Z0)
+    odZ, ofa, of3 = oracle_signals(Zd, Z0)
+    assert np.allclose(dZ, odZ, rtol=0, atol=1e-15)
+    assert np.allclose(fa, ofa, rtol=0, atol=1e-15) and np.allclose(f3, of3, rtol=0, atol=1e-15)
+    dZ2, fa2, f32 = eddy.ect_signals(dZ)
+    assert np.array_equal(dZ2, dZ) and np.allclose(fa2, ofa, rtol=0, atol=1e-15)
+    assert eddy.ect_signals(np.zeros((0, 2, 2)))[1].shape == (0,)
