@@ -289,6 +289,7 @@ def main():
                         "kernels": runs["fp64"]["kernels"]} if "fp64" in runs and head != "fp64" else None),
         "batched_scan": scan,
         "host_setup_s": round(host_setup, 2),
+        "spmv_tuning": op.tuning(),
         "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -91,9 +91,25 @@ typedef struct {
   double div_residual; /* ||G^T b_A|| / ||b||: discrete divergence of the source   */
   int32_t precision_used;  /* 1 if the complex64 inner loop ran (mixed mode needs */
                            /* the penalty-free operator; else FP64 is used)        */
-  int32_t reorth_steps;    /* Arnoldi steps that needed the second Gram-Schmidt    */
-                           /* pass (norm dropped below 1/sqrt(2) of ||w||)         */
+  int32_t reorth_steps;    /* Arnoldi steps whose basis vector got the second      */
+                           /* Gram-Schmidt pass: every step in eddy_solve (delayed */
+                           /* scheme); in eddy_solve_batched, the steps where the  */
+                           /* norm dropped below 1/sqrt(2) of ||w||                */
 } eddy_solve_report;
+
+/* Launch shapes the operator picked by timing candidates on its own matrix
+ * at its first eddy_op_assemble (see eddy_op_tuning). */
+typedef struct {
+  int32_t spmv_grid_full;   /* workgroups of an uncapped SpMV launch (one per 4 slices) */
+  int32_t spmv_grid_c128;   /* chosen cap for the complex128 SpMV (0 = uncapped)       */
+  int32_t spmv_grid_c64;    /* chosen cap for the complex64 SpMV (0 = uncapped)        */
+  int32_t spmv_sched_c128;  /* chosen schedule: 0 all XCDs sweep the rows together,    */
+  int32_t spmv_sched_c64;   /*   1 each XCD takes a contiguous range of rows           */
+  float spmv_us_c128;       /* measured time per SpMV at the chosen shape, microseconds */
+  float spmv_us_c64;
+  float spmv_us_sched_c128[2];  /* best time of each schedule                          */
+  float spmv_us_sched_c64[2];
+} eddy_tuning;
 
 /* ---- mesh (host) -------------------------------------------------------
  * eddy_mesh_create: nv nodes xyz[nv*3] (host, metres), nt tetrahedra
@@ -237,12 +253,16 @@ eddy_status eddy_export(const eddy_op* op, int32_t* rowptr, int32_t* col, eddy_c
 
 /* Per-kernel-class timing of the GMRES loop, measured with HIP events on the
  * solve's stream and read at the loop's per-iteration synchronisation.
- * Classes: 0 block-Jacobi apply, 1 gauge product W~^T x, 2 CSR SpMV
+ * Classes: 0 block-Jacobi apply, 1 gauge product W~^T x, 2 SpMV
  * (+ W~ t), 3 CGS2 orthogonalisation + normalisation.  Returns (host) the
  * accumulated milliseconds ms[4] and launch counts counts[4] since the
  * previous call (either may be NULL), resets them, and turns timing on
  * (enable != 0) or off.  Creating the events is the only allocation. */
 eddy_status eddy_profile(eddy_op* op, int32_t enable, double* ms, int64_t* counts);
+/* The SpMV grid caps chosen at the first eddy_op_assemble (an autotuner: each
+ * candidate cap is timed with HIP events on the operator's own sliced-ELL
+ * matrix; the cap changes no result, only which workgroup runs a slice). */
+eddy_status eddy_op_tuning(const eddy_op* op, eddy_tuning* out);
 
 const char* eddy_status_string(eddy_status status);
 const char* eddy_last_error(void);

@@ -54,7 +54,7 @@ struct Carve {
 using namespace eddy;
 
 struct eddy_op {
-  int64_t nv, nt, ne, nc, nct, n, nnz, nnzw, nb;
+  int64_t nv, nt, ne, nc, nct, n, nnz, nnzw, nb, ns, nsell;
   int32_t nreg, ncomp, bsize;
   uint64_t geom_hash;
   double tau, tau_p, delta_v, omega = 0;
@@ -68,10 +68,15 @@ struct eddy_op {
   int *wrowptr, *wcol, *wcptr, *wclist, *wtrowptr, *wtcol, *wtperm;
   int *d0ptr, *d0list, *lcptr, *lclist, *rptr, *rlist;
   int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
+  int *sell_ptr, *sell_row, *sell_col, *sell_src;
   // numeric
   double2 *val, *ebuf, *minv;
   double* gscr;                 // gauge part of the diagonal blocks (assembly scratch)
   float2 *val32, *minv32;       // complex64 copies for the mixed-precision inner loop
+  double2* sval;                // sliced ELL values (complex128 and complex64)
+  float2* sval32;
+  eddy_tuning tune = {};        // SpMV grid caps (autotuned at the first assembly)
+  bool tuned = false;
   double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *d0taup, *lumped, *s, *nu_reg, *sig_reg;
   double2 *tmp1, *tmp2, *tvec, *red;
   double* rred;
@@ -127,6 +132,13 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->blk_dofs = c.take<int>(m->ndof());
   o->blk_of = c.take<int>(m->ndof());
   o->loc_of = c.take<int>(m->ndof());
+  const int64_t ns = (int64_t)m->sell_ptr.size() - 1, nsell = (int64_t)m->sell_col.size();
+  o->sell_ptr = c.take<int>(ns + 1);
+  o->sell_row = c.take<int>(ns * kSellC);
+  o->sell_col = c.take<int>(nsell);
+  o->sell_src = c.take<int>(nsell);
+  o->sval = c.take<double2>(nsell);
+  o->sval32 = c.take<float2>(nsell);
   o->val = c.take<double2>(m->nnz());
   o->ebuf = c.take<double2>(21 * m->nt + 34 * m->nct);
   o->minv = c.take<double2>(nb * kMaxBlock * kMaxBlock);
@@ -184,11 +196,56 @@ eddy_status upload(T* dst, const std::vector<T>& src, hipStream_t st) {
 
 // y = M~ x (scaled system; gauge term included if `gauge`); `t` is the
 // node-sized gauge temporary.
+// Time `reps` SpMV launches per candidate (schedule, grid cap) and keep the
+// fastest; also record the best time of each schedule.
+template <class T>
+eddy_status tune_spmv(eddy_op* o, const T* sval, T* x, T* y, int* best_grid, int* best_sched, float* best_us,
+                      float* sched_us, hipStream_t s) {
+  const int full = spmv_full_grid(o->ns);
+  const int caps[] = {0, 4096, 2048, 1024, 512};
+  constexpr int reps = 4;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); set_error("hipEventCreate"); return EDDY_ERR_DEVICE; }
+  eddy_status st = EDDY_OK;
+  *best_grid = 0;
+  *best_sched = 0;
+  *best_us = 1e30f;
+  sched_us[0] = sched_us[1] = 1e30f;
+  for (int sch = 0; sch < 2 && st == EDDY_OK; ++sch)
+    for (int g : caps) {
+      if (g >= full) continue;
+      launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, sval, o->ne, nullptr, nullptr, nullptr, nullptr, x,
+                  nullptr, y, s, g, sch);
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r)
+        launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, sval, o->ne, nullptr, nullptr, nullptr, nullptr,
+                    x, nullptr, y, s, g, sch);
+      (void)hipEventRecord(e1, s);
+      float ms = 0;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        set_error("SpMV tuning: event timing failed");
+        st = EDDY_ERR_DEVICE;
+        break;
+      }
+      const float us = 1e3f * ms / reps;
+      sched_us[sch] = std::min(sched_us[sch], us);
+      if (us < *best_us) {
+        *best_us = us;
+        *best_grid = g;
+        *best_sched = sch;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 void op_spmv(const eddy_op* o, const double2* x, const double2* b, double2* y, double2* t, hipStream_t st,
              bool gauge = true) {
   if (gauge) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, x, t, st);
-  launch_spmv(o->n, o->ne, o->rowptr, o->col, o->val, gauge ? o->wrowptr : nullptr, o->wcol, o->wval, t, x, b, y,
-              st);
+  launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, o->sval, o->ne, gauge ? o->wrowptr : nullptr, o->wcol,
+              o->wval, t, x, b, y, st, o->tune.spmv_grid_c128, o->tune.spmv_sched_c128);
 }
 
 }  // namespace
@@ -314,6 +371,8 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   o->nnz = m->nnz(); o->nnzw = m->nnzw(); o->nb = (int64_t)m->blk_ptr.size() - 1;
   o->nreg = m->nreg; o->ncomp = m->ncomp; o->bsize = p->block_size;
   o->geom_hash = m->geom_hash;
+  o->ns = (int64_t)m->sell_ptr.size() - 1;
+  o->nsell = (int64_t)m->sell_col.size();
   o->tau = p->tau_gauge; o->delta_v = p->delta_v;
   o->tau_p = p->tau_precond > 0 ? p->tau_precond : p->tau_gauge;
   o->is_cond = m->is_cond;
@@ -335,6 +394,8 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   UP(o->d0ptr, m->d0ptr); UP(o->d0list, m->d0list); UP(o->lcptr, m->lcptr); UP(o->lclist, m->lclist);
   UP(o->rptr, m->rptr); UP(o->rlist, m->rlist); UP(o->blk_ptr, m->blk_ptr); UP(o->blk_dofs, m->blk_dofs);
   UP(o->blk_of, blk_of); UP(o->loc_of, loc_of);
+  UP(o->sell_ptr, m->sell_ptr); UP(o->sell_row, m->sell_row); UP(o->sell_col, m->sell_col);
+  UP(o->sell_src, m->sell_src);
 #undef UP
   if (r == EDDY_OK) {
     hipError_t e = hipStreamSynchronize(s);   // host vectors are freed after return
@@ -378,12 +439,25 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
                       o->wrowptr, o->wcol, o->wval, o->d0taup, o->gscr, o->minv, o->status, s);
   launch_to_c64(o->nnz, o->val, o->val32, s);
   launch_to_c64(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv32, s);
+  launch_sell_gather(o->nsell, o->sell_src, o->val, o->sval, o->sval32, s);
   HIP_TRY(hipGetLastError());
   int stat = 0;
   HIP_TRY(hipMemcpyAsync(&stat, o->status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (stat & 2) { set_error("zero diagonal entry in M"); return EDDY_ERR_SINGULAR_BLOCK; }
   if (stat & 1) { set_error("zero pivot in a block-Jacobi block"); return EDDY_ERR_SINGULAR_BLOCK; }
+  if (!o->tuned) {   // the pattern fixes the best launch shape: tune at the first assembly only
+    eddy_tuning& t = o->tune;
+    t.spmv_grid_full = (int32_t)spmv_full_grid(o->ns);
+    launch_zero(o->n, o->tmp1, s);
+    eddy_status ts = tune_spmv<double2>(o, o->sval, o->tmp1, o->tmp2, &t.spmv_grid_c128, &t.spmv_sched_c128,
+                                        &t.spmv_us_c128, t.spmv_us_sched_c128, s);
+    if (ts == EDDY_OK)
+      ts = tune_spmv<float2>(o, o->sval32, (float2*)o->tmp1, (float2*)o->tmp2, &t.spmv_grid_c64, &t.spmv_sched_c64,
+                             &t.spmv_us_c64, t.spmv_us_sched_c64, s);
+    if (ts != EDDY_OK) return ts;
+    o->tuned = true;
+  }
   o->assembled = true;
   return EDDY_OK;
 }
@@ -455,6 +529,10 @@ struct SolveWs {
   double2 *Hd, *snd, *gd;
   double *csd, *est, *nrm1;
   int *flag, *nreorth;
+  // DCGS2: unrotated Hessenberg (column-major, ld m + 1), fused dots, step
+  // coefficients, zeros, ||t|| of the pending direction
+  double2 *Hraw, *dots, *coef, *zeros;
+  double* tnorm;
 };
 inline int64_t basis_ld(int64_t n) { return (n + 63) / 64 * 64; }   // 512-B aligned basis vectors
 
@@ -480,6 +558,11 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->nrm1 = c.take<double>(8);
   w->flag = c.take<int>(8);
   w->nreorth = c.take<int>(8);
+  w->Hraw = c.take<double2>((int64_t)(m + 1) * m);
+  w->dots = c.take<double2>(2 * kMaxRestart + 4);
+  w->coef = c.take<double2>(2 * kMaxRestart + 4);
+  w->zeros = c.take<double2>(kMaxRestart + 2);
+  w->tnorm = c.take<double>(8);
   w->V = c.take<double2>(mixed ? 0 : (int64_t)(m + 1) * basis_ld(n));
   w->w = c.take<double2>(n);
   w->z = c.take<double2>(n);
@@ -489,7 +572,7 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->h2 = c.take<double2>(kMaxRestart + 2);
   w->hd = c.take<double2>(kMaxRestart + 2);
   w->yd = c.take<double2>(kMaxRestart + 2);
-  w->part = c.take<double2>((int64_t)(mdot_parts(n > nv ? n : nv) + kRedBlocks) * (m + 2));
+  w->part = c.take<double2>((int64_t)(mdot_parts(n > nv ? n : nv) + kRedBlocks) * (2 * m + 4));
   w->rpart = c.take<double>(kRedBlocks + 8);
   w->nrm = c.take<double>(8);
   return c.off + 256;
@@ -586,7 +669,7 @@ struct Inner {
   T* V;
   T* w;
   T* z;
-  const T* val;
+  const T* sval;     // sliced ELL values
   const T* minv;
 };
 
@@ -609,56 +692,68 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
   std::vector<double> est(m + 1);
   double beta = bnorm;
   const double2* r = W.bt;     // r0 = b~ (x0 = 0), FP64
+  const int nparts = mdot2_parts(n);
+  const double2 zero2h[kMaxRestart + 2] = {};
+  HIP_TRY(hipMemcpyAsync(W.zeros, zero2h, sizeof(zero2h), hipMemcpyHostToDevice, s));
   while (true) {
+    // pending vector v_0 = r / beta; the DCGS2 step j finishes v_j and
+    // projects the next direction once (see k_dcgs_coef)
     launch_scale_host(n, r, 1.0 / beta, I.V, s);
-    int k = 0, jstart = 0;
+    int k = 0, jstart = 0;     // jstart: first estimate index not yet checked
     bool stop = false;
     for (int j = 0; j < m; ++j) {
       T* vj = I.V + (int64_t)j * ld;
-      hipEvent_t* ev = o->ev + 5 * (j - jstart);
+      hipEvent_t* ev = o->ev + 5 * ((j % kCheckEvery));
       if (o->profile) (void)hipEventRecord(ev[0], s);
       launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, vj, I.z, s);
       if (o->profile) (void)hipEventRecord(ev[1], s);
       if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, (const double2*)I.z, o->tvec, s);
       if (o->profile) (void)hipEventRecord(ev[2], s);
-      launch_spmv(o->n, o->ne, o->rowptr, o->col, I.val, gauge_op ? o->wrowptr : nullptr, o->wcol, o->wval, o->tvec,
-                  (const T*)I.z, nullptr, I.w, s);
+      launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, I.sval, o->ne, gauge_op ? o->wrowptr : nullptr,
+                  o->wcol, o->wval, o->tvec, (const T*)I.z, nullptr, I.w, s,
+                  std::is_same<T, float2>::value ? o->tune.spmv_grid_c64 : o->tune.spmv_grid_c128,
+                  std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128);
       if (o->profile) (void)hipEventRecord(ev[3], s);
-      // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, ||w|| (FP64 accumulation)
-      const int q = j + 1;
-      // first pass (+ ||w||^2), then the second pass only when needed
-      launch_mdot(n, (const T*)I.V, ld, q, (const T*)I.w, W.part, s, 1);
-      launch_reduce_cols(q + 1, mdot_parts(n), W.part, W.h1, s);
-      launch_update_norm(n, (const T*)I.V, ld, q, W.h1, I.w, W.rpart, W.nrm1, s);
-      launch_reorth_decide(q, W.h1, W.nrm1, W.h2, W.nrm, W.flag, W.nreorth, s);
-      launch_mdot(n, (const T*)I.V, ld, q, (const T*)I.w, W.part, s, 0, W.flag);
-      launch_reduce_cols(q, mdot_parts(n), W.part, W.h2, s, W.flag);
-      launch_update_norm(n, (const T*)I.V, ld, q, W.h2, I.w, W.rpart, W.nrm, s, W.flag);
-      launch_scale_by_inv(n, (const T*)I.w, W.nrm, I.V + (int64_t)(j + 1) * ld, s);
+      launch_mdot2(n, (const T*)I.V, ld, j, (const T*)vj, (const T*)I.w, W.part, s);
+      launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);
+      launch_dcgs_coef(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est, s);
+      launch_dcgs_update(n, (const T*)I.V, ld, j, W.coef, vj, I.w, W.rpart, W.tnorm, s);
+      launch_scale_by_inv(n, (const T*)I.w, W.tnorm, I.V + (int64_t)(j + 1) * ld, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
-      launch_givens(j, m, W.h1, W.h2, W.nrm, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est, s);
       ++it;
-      const bool check = (j + 1 - jstart) == kCheckEvery || j == m - 1 || it >= opts->max_iter;
+      const bool last = j == m - 1 || it >= opts->max_iter;
+      const bool check = last || (j + 1) % kCheckEvery == 0;
       if (!check) continue;
-      HIP_TRY(hipMemcpyAsync(est.data() + jstart, W.est + jstart, sizeof(double) * (j + 1 - jstart),
-                             hipMemcpyDeviceToHost, s));
+      // estimates after 1..j steps are final; at the end of a cycle the last
+      // column (projected once) also gets its rotation
+      int avail = j;
+      if (last) {
+        launch_givens(j, m, W.Hraw + (int64_t)j * (m + 1), W.zeros, W.tnorm, W.Hd, W.csd, W.snd, W.gd, beta, bnorm,
+                      W.est, s);
+        avail = j + 1;
+      }
+      if (avail > jstart)
+        HIP_TRY(hipMemcpyAsync(est.data() + jstart, W.est + jstart, sizeof(double) * (avail - jstart),
+                               hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       if (o->profile) {
-        for (int jj = 0; jj <= j - jstart; ++jj)
+        const int j0 = j + 1 - ((j % kCheckEvery) + 1);
+        for (int jj = j0; jj <= j; ++jj)
           for (int c = 0; c < 4; ++c) {
             float ms = 0;
-            if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, o->ev[5 * jj + c], o->ev[5 * jj + c + 1]) == hipSuccess) {
+            hipEvent_t* e = o->ev + 5 * (jj % kCheckEvery);
+            if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, e[c], e[c + 1]) == hipSuccess) {
               o->prof_ms[c] += ms;
               o->prof_n[c] += 1;
             }
           }
       }
-      for (int jj = jstart; jj <= j; ++jj) {
+      for (int jj = jstart; jj < avail; ++jj) {
         if (!std::isfinite(est[jj])) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
         if (est[jj] <= opts->tol) {
           if (est[jj] == 0.0) R.breakdown = 1;
-          it -= j - jj;       // steps after jj were computed but are not used
           k = jj + 1;
+          it -= (j + 1) - k;    // steps after k were computed but are not used
           stop = true;
           break;
         }
@@ -668,7 +763,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
         stop = true;
       }
       if (stop) break;
-      jstart = j + 1;
+      jstart = avail;
     }
     if (!stop) k = m;
     R.est_relres = est[k - 1];
@@ -747,7 +842,6 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
     if (R.div_residual > 1e-10) gauge_op = true;
   }
   R.gauge_in_operator = gauge_op ? 1 : 0;
-  HIP_TRY(hipMemsetAsync(W.nreorth, 0, sizeof(int), s));
   // equilibrated right-hand side b~ = s b, x~ = 0
   launch_diag_scale(n, (const double2*)b_dev, o->s, 0, W.bt, s);
   launch_zero(n, W.xt, s);
@@ -763,10 +857,10 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   R.precision_used = mixed ? 1 : 0;
   if (bnorm > 0) {
     if (mixed) {
-      Inner<float2> I{W.V32, W.w32, W.z32, o->val32, o->minv32};
+      Inner<float2> I{W.V32, W.w32, W.z32, o->sval32, o->minv32};
       st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
     } else {
-      Inner<double2> I{W.V, W.w, W.z, o->val, o->minv};
+      Inner<double2> I{W.V, W.w, W.z, o->sval, o->minv};
       st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
     }
     if (st != EDDY_OK) return st;
@@ -780,8 +874,7 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   R.iters = it;
-  HIP_TRY(hipMemcpyAsync(&R.reorth_steps, W.nreorth, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  R.reorth_steps = it;     // the delayed scheme reorthogonalises every basis vector
   R.converged = R.relres <= opts->tol ? 1 : 0;
   R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = R;
@@ -1091,6 +1184,13 @@ eddy_status eddy_impedance(const eddy_op* o, int32_t nsol, const eddy_c128* x_de
       Z[k * nsrc + l].re = z.real();
       Z[k * nsrc + l].im = z.imag();
     }
+  return EDDY_OK;
+}
+
+eddy_status eddy_op_tuning(const eddy_op* o, eddy_tuning* out) {
+  if (!o || !out) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+  *out = o->tune;
   return EDDY_OK;
 }
 

@@ -48,6 +48,20 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 
+// Loads of data read exactly once (matrix values and indices): non-temporal,
+// so that they do not evict reused data (the gathered vector) from the L2.
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const v2d_t v = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const v2f_t v = __builtin_nontemporal_load(reinterpret_cast<const v2f_t*>(p));
+  return make_float2(v.x, v.y);
+}
+
 // ---- storage-type helpers: complex128 (double2) or complex64 (float2) ----
 __device__ __forceinline__ double2 ld2(double2 a) { return a; }
 __device__ __forceinline__ double2 ld2(float2 a) { return make_double2(a.x, a.y); }

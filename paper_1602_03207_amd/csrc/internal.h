@@ -28,7 +28,12 @@ constexpr int kMaxBlock = 64;       // block-Jacobi block size limit (LDS-reside
 constexpr int kMaxRestart = 64;
 constexpr int kMaxWRow = 32;       // max nodes adjacent to one edge (LDS-staged gauge blocks)
 constexpr int kBatchChunk = 8;     // systems per pass of the batched SpMV / block-Jacobi kernels
-constexpr int kMaxDzCols = 4;      // free-configuration solutions per pass of the defect-volume kernel
+constexpr int kMaxDzCols = 4;
+// Sliced ELL copy of M for the SpMV: slices of kSellC rows (one wavefront,
+// one lane per row), rows sorted by decreasing length inside windows of
+// kSellWindow rows; slice s holds its width x kSellC entries column-major.
+constexpr int kSellC = 64;
+constexpr int kSellWindow = 1024;      // free-configuration solutions per pass of the defect-volume kernel
 
 inline int pair6(int l, int m) {    // upper-triangle slot of a symmetric 6x6
   if (l > m) { int t = l; l = m; m = t; }
@@ -69,6 +74,10 @@ struct eddy_mesh {
   std::vector<int32_t> wtrowptr, wtcol, wtperm;
   // gathers of vol4 (D0 over all tets, lumped conductor mass) and of rbuf
   std::vector<int32_t> d0ptr, d0list, lcptr, lclist, rptr, rlist;
+  // sliced ELL: sell_ptr[nslices+1] (entry offsets), sell_row[nslices*kSellC]
+  // (row of each lane, -1 past the end), sell_col / sell_src per entry (CSR
+  // position of the value, -1 for padding, whose column is the lane's row)
+  std::vector<int32_t> sell_ptr, sell_row, sell_col, sell_src;
   // cached block partition
   int32_t blk_b = 0;
   std::vector<int32_t> blk_ptr, blk_dofs;

@@ -37,11 +37,18 @@ void launch_rhs_elem(int64_t nt, const double* xyz, const int* tet, const uint8_
 void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const double* d0tau,
                const double2* x, double2* t, hipStream_t st);
 // y = M~ x + W~ t  (A rows, if wrowptr); if b != nullptr: y = b - (...).
-// T = double2 (complex128) or float2 (complex64) storage and arithmetic.
+// M~ in the sliced ELL layout (ns slices); T = double2 (complex128) or float2
+// (complex64) storage and arithmetic.  grid > 0 caps the number of
+// workgroups; schedule 0 sweeps the slices with all XCDs together, 1 gives
+// each XCD a contiguous range.  Neither changes the result.
 template <class T>
-void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const T* val, const int* wrowptr,
-                 const int* wcol, const double* wval, const double2* t, const T* x, const double2* b, T* y,
-                 hipStream_t st);
+void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, const T* sval, int64_t ne,
+                 const int* wrowptr, const int* wcol, const double* wval, const double2* t, const T* x,
+                 const double2* b, T* y, hipStream_t st, int grid = 0, int schedule = 0);
+// workgroups of an uncapped SpMV launch over ns slices
+int spmv_full_grid(int64_t ns);
+void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2* sval, float2* sval32,
+                        hipStream_t st);
 template <class T>
 void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, const T* r, T* z,
                         hipStream_t st);
@@ -55,10 +62,6 @@ void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2*
 int mdot_parts(int64_t n);
 void launch_reduce_cols(int q, int nparts, const double2* partial, double2* out, hipStream_t st,
                         const int* flag = nullptr);
-void launch_reorth_decide(int q, const double2* h1, const double* nrm1, double2* h2, double* nrm, int* flag,
-                          int* counter, hipStream_t st);
-template <class T>
-void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, hipStream_t st);
 template <class T>
 void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipStream_t st);
 template <class T>
@@ -70,10 +73,6 @@ void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y,
 template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st);
 void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
-// second CGS2 update fused with the norm of the new vector
-template <class T>
-void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
-                        double* out_norm, hipStream_t st, const int* flag = nullptr);
 // ---- batched systems (vectors of system r at offset r * stride; grid.z = r;
 // `active` (device int[nrhs], may be null) masks systems out)
 template <class T>
@@ -116,6 +115,20 @@ void launch_diag_scale_b(int64_t n, const double2* in, int64_t istride, const do
 template <class T>
 void launch_to_storage_b(int64_t n, const double2* in, int64_t istride, T* out, int64_t ostride, int nrhs,
                          hipStream_t st);
+// Arnoldi by CGS2 with delayed reorthogonalisation (DCGS2): fused dots
+// [V^H v, V^H w, v^H v, v^H w] (2q + 2 partial columns of mdot2_parts(n)),
+// the step's small linear algebra + lagged Givens rotation, and the fused
+// update (finished basis vector into v, next direction into w, ||w||).
+int mdot2_parts(int64_t n);
+template <class T>
+void launch_mdot2(int64_t n, const T* V, int64_t ldv, int q, const T* v, const T* w, double2* partial,
+                  hipStream_t st);
+void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
+                      double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
+                      hipStream_t st);
+template <class T>
+void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,
+                        double* out_norm, hipStream_t st);
 // Hessenberg least squares on the device
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);

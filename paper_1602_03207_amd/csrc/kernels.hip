@@ -520,30 +520,84 @@ __global__ __launch_bounds__(kThreads) void k_project(int64_t ne, int64_t nc, co
 
 // y = M~ x (+ W~ t on A rows if wrowptr), 8 lanes per row; y = b - (...) if b.
 // Arithmetic in the storage precision T.
+// y = M x (or b - M x) on the sliced ELL copy: one wavefront per slice, one
+// lane per row; each step of the loop reads 64 consecutive values and column
+// indices (streamed past the L2), the slice width is uniform over the
+// wavefront.  Workgroups loop over groups of 4 slices.  Schedule 0: group g,
+// g + grid, ... (all XCDs sweep the rows together).  Schedule 1: workgroups
+// are dispatched round-robin over the kXcds XCDs (workgroup i on XCD i mod
+// kXcds), and each XCD takes a contiguous range of groups, so the rows
+// sharing gathered x entries stay under one L2.  Each row's sum has the same
+// order in every schedule and grid size.
+constexpr int kXcds = 8;
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_spmv(int64_t n, int64_t ne, const int* __restrict__ rowptr,
-                                                   const int* __restrict__ col, const T* __restrict__ val,
-                                                   const int* __restrict__ wrowptr, const int* __restrict__ wcol,
-                                                   const double* __restrict__ wval, const double2* __restrict__ t,
-                                                   const T* __restrict__ x, const double2* __restrict__ b,
-                                                   T* __restrict__ y) {
+__global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* __restrict__ sptr,
+                                                        const int* __restrict__ srow, const int* __restrict__ scol,
+                                                        const T* __restrict__ sval, const T* __restrict__ x,
+                                                        const double2* __restrict__ b, T* __restrict__ y,
+                                                        int schedule) {
+  static_assert(kSellC == 64, "one wavefront per slice");
+  constexpr int kGroup = kThreads / 64;
+  const int l = threadIdx.x & 63;
+  const int64_t ngroups = (ns + kGroup - 1) / kGroup;
+  int64_t g0, g1, gstep;
+  if (schedule == 0) {
+    g0 = blockIdx.x;
+    g1 = ngroups;
+    gstep = gridDim.x;
+  } else {
+    const int64_t xcd = blockIdx.x % kXcds, q = blockIdx.x / kXcds;
+    const int64_t nwg = gridDim.x / kXcds + (xcd < (int64_t)(gridDim.x % kXcds) ? 1 : 0);
+    g0 = ngroups * xcd / kXcds + q;
+    g1 = ngroups * (xcd + 1) / kXcds;
+    gstep = nwg;
+  }
+  for (int64_t g = g0; g < g1; g += gstep) {
+    const int64_t s = g * kGroup + (threadIdx.x >> 6);
+    if (s >= ns) break;
+    const int row = srow[s * kSellC + l];
+    const int p0 = sptr[s];
+    const int w = (sptr[s + 1] - p0) / kSellC;
+    const int* __restrict__ c = scol + p0 + l;
+    const T* __restrict__ v = sval + p0 + l;
+    T acc = zero2<T>();
+#pragma unroll 4
+    for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+    if (row >= 0) y[row] = b ? st2<T>(csub(b[row], ld2(acc))) : acc;
+  }
+}
+
+// y_A += sign * W t over the A rows (factored gauge term; kLanes lanes per row).
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_gauge_add(int64_t ne, const int* __restrict__ wrowptr,
+                                                        const int* __restrict__ wcol, const double* __restrict__ wval,
+                                                        const double2* __restrict__ t, double sign,
+                                                        T* __restrict__ y) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
   const int lane = threadIdx.x % kLanes;
-  T acc = zero2<T>();
-  if (row < n) {
-    for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) acc = cfmaT(val[p], x[col[p]], acc);
-    if (wrowptr && row < ne) {
-      double2 ga = make_double2(0.0, 0.0);
-      for (int p = wrowptr[row] + lane; p < wrowptr[row + 1]; p += kLanes) ga = rfma(wval[p], t[wcol[p]], ga);
-      acc.x += ga.x;
-      acc.y += ga.y;
-    }
-  }
+  double2 ga = make_double2(0.0, 0.0);
+  if (row < ne)
+    for (int p = wrowptr[row] + lane; p < wrowptr[row + 1]; p += kLanes) ga = rfma(wval[p], t[wcol[p]], ga);
   for (int o = kLanes / 2; o > 0; o >>= 1) {
-    acc.x += __shfl_xor(acc.x, o, kLanes);
-    acc.y += __shfl_xor(acc.y, o, kLanes);
+    ga.x += __shfl_xor(ga.x, o, kLanes);
+    ga.y += __shfl_xor(ga.y, o, kLanes);
   }
-  if (row < n && lane == 0) y[row] = b ? st2<T>(csub(b[row], ld2(acc))) : acc;
+  if (row < ne && lane == 0) {
+    const double2 yo = ld2(y[row]);
+    y[row] = st2<T>(make_double2(fma(sign, ga.x, yo.x), fma(sign, ga.y, yo.y)));
+  }
+}
+
+// Values of the sliced ELL copy from the CSR values (padding = 0).
+__global__ __launch_bounds__(kThreads) void k_sell_gather(int64_t tot, const int* __restrict__ src,
+                                                          const double2* __restrict__ val, double2* __restrict__ sval,
+                                                          float2* __restrict__ sval32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const int p = src[i];
+  const double2 v = p >= 0 ? val[p] : make_double2(0.0, 0.0);
+  sval[i] = v;
+  sval32[i] = make_float2((float)v.x, (float)v.y);
 }
 
 // z_I = Minv_I r_I, one 64-lane wavefront per block, 4 blocks per workgroup.
@@ -566,7 +620,7 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int*
   if (dof < 0) return;
   const T* Mk = minv + k * kMaxBlock * kMaxBlock;
   T acc = zero2<T>();
-  for (int j = 0; j < sz; ++j) acc = cfmaT(Mk[j * kMaxBlock + i], rl[w][j], acc);
+  for (int j = 0; j < sz; ++j) acc = cfmaT(ld_stream(Mk + j * kMaxBlock + i), rl[w][j], acc);
   z[dof] = acc;
 }
 
@@ -627,6 +681,102 @@ __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restric
   }
 }
 
+// ---- Arnoldi by classical Gram-Schmidt with delayed reorthogonalisation
+// (DCGS2: the second projection of basis vector j is fused with the first
+// projection of the next direction; Swirydowicz, Langou, Ananthan, Yang and
+// Thomas, Low synchronization Gram-Schmidt and GMRES algorithms, Numer.
+// Linear Algebra Appl. 2021).  Per Arnoldi step the basis is read twice
+// (one fused dot pass, one fused update pass) instead of four times.
+//
+// Fused dots of the pending vector v and the new direction w against the q
+// finished basis vectors, one read of V: partial columns k < q: V_k^H v,
+// q + k: V_k^H w, 2q: v^H v, 2q + 1: v^H w (FP64 accumulation).  Workgroup
+// (x, y) takes the vectors 8y..8y+7 and the tiles of kDot2Rows rows
+// x, x + gridDim.x, ... (kDot2Rows / 256 rows per thread and tile), so the
+// wavefront reductions happen once per workgroup; slice y = 0 also forms
+// v^H v and v^H w.
+constexpr int kDot2Rows = 2 * kThreads;
+constexpr int kDot2MaxBlocks = 1024;
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                    const T* __restrict__ v, const T* __restrict__ w,
+                                                    double2* __restrict__ partial) {
+  constexpr int R = kDot2Rows / kThreads;
+  __shared__ double2 red[4][18];
+  const int c0 = blockIdx.y * 8;
+  const int cnt = max(0, min(8, q - c0));
+  const bool norms = blockIdx.y == 0;
+  double2 as[8], ar[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    as[k] = make_double2(0.0, 0.0);
+    ar[k] = make_double2(0.0, 0.0);
+  }
+  double aa = 0.0;
+  double2 bb = make_double2(0.0, 0.0);
+  for (int64_t base = (int64_t)blockIdx.x * kDot2Rows + threadIdx.x; base < n;
+       base += (int64_t)gridDim.x * kDot2Rows) {
+    double2 vr[R], wr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = base + (int64_t)r * kThreads;
+      vr[r] = i < n ? ld2(v[i]) : make_double2(0.0, 0.0);
+      wr[r] = i < n ? ld2(w[i]) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < cnt) {
+        const T* Vk = V + (int64_t)(c0 + k) * ldv;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int64_t i = base + (int64_t)r * kThreads;
+          if (i < n) {
+            const double2 x = ld2(Vk[i]);
+            as[k] = cfma_conj(x, vr[r], as[k]);
+            ar[k] = cfma_conj(x, wr[r], ar[k]);
+          }
+        }
+      }
+    if (norms) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        aa = fma(vr[r].x, vr[r].x, fma(vr[r].y, vr[r].y, aa));
+        bb = cfma_conj(vr[r], wr[r], bb);
+      }
+    }
+  }
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k < cnt) {
+      const double sr = wave_sum(as[k].x), si = wave_sum(as[k].y);
+      const double rr = wave_sum(ar[k].x), ri = wave_sum(ar[k].y);
+      if (ln == 0) {
+        red[wv][k] = make_double2(sr, si);
+        red[wv][8 + k] = make_double2(rr, ri);
+      }
+    }
+  if (norms) {
+    aa = wave_sum(aa);
+    bb.x = wave_sum(bb.x);
+    bb.y = wave_sum(bb.y);
+    if (ln == 0) {
+      red[wv][16] = make_double2(aa, 0.0);
+      red[wv][17] = bb;
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  int col = -1;
+  if (t < 16 && (t & 7) < cnt) col = (t < 8 ? 0 : q) + c0 + (t & 7);
+  if (norms && (t == 16 || t == 17)) col = 2 * q + (t - 16);
+  if (col >= 0) {
+    const double2 r = make_double2((red[0][t].x + red[1][t].x) + (red[2][t].x + red[3][t].x),
+                                   (red[0][t].y + red[1][t].y) + (red[2][t].y + red[3][t].y));
+    partial[(int64_t)col * gridDim.x + blockIdx.x] = r;
+  }
+}
+
 // out[k] = sum_b partial[k * kRedBlocks + b]  (fixed tree per column)
 __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restrict__ partial, int nparts,
                                                           double2* __restrict__ out, const int* __restrict__ flag,
@@ -648,24 +798,6 @@ __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double2* __restr
   if (threadIdx.x == 0) out[k] = make_double2(re, im);
 }
 
-// w -= sum_k V_k h_k  (FP64 arithmetic, stored in T)
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_update(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                     const double2* __restrict__ h, T* __restrict__ w) {
-  __shared__ double2 hs[kMaxRestart + 1];
-  if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double2 acc = ld2(w[i]);
-  for (int k = 0; k < q; ++k) {
-    const double2 v = ld2(V[(int64_t)k * ldv + i]);
-    const double2 hk = hs[k];
-    acc.x -= v.x * hk.x - v.y * hk.y;
-    acc.y -= v.x * hk.y + v.y * hk.x;
-  }
-  w[i] = st2<T>(acc);
-}
 
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_norm2_partial(int64_t n, const T* __restrict__ w,
@@ -877,6 +1009,166 @@ __global__ void k_givens(int j, int m, const double2* __restrict__ h1, const dou
                          double* __restrict__ est) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   givens_body(j, m, h1, h2, nrm, H, cs, sn, g, beta, bnorm, est);
+}
+
+// Small linear algebra of DCGS2 step j (one workgroup of 64 threads).  In:
+// dots = [s = Q^H v (j), r = Q^H w (j), v^H v, v^H w] with Q the j finished
+// basis vectors, v the pending vector (projected once), w the operator
+// applied to v; Hraw the unrotated Hessenberg matrix (column-major, leading
+// dimension m + 1) whose column j - 1 still holds the once-projected
+// coefficients h and tnorm = ||t|| of the previous step (v = t / ||t||).
+// With rho = ||v - Q s|| = sqrt(v^H v - |s|^2) (Pythagoras, Q orthonormal):
+//   q_j = (v - Q s) / rho;  column j - 1 becomes h + ||t|| s, subdiagonal ||t|| rho;
+//   A q_j = (w - Q H(0:j,0:j) s - q_j H(j,j-1) s_{j-1}) / rho, whose
+//   coefficients are c = (r - H s) / rho and c_j = ((v^H w - s^H r) / rho
+//   - H(j,j-1) s_{j-1}) / rho;  the next direction
+//   t' = A q_j - Q c - q_j c_j = w / rho - kappa v / rho - Q g with
+//   kappa = H(j,j-1) s_{j-1} / rho + c_j and g = H s / rho + c - kappa s / rho.
+// Out: coef = [s (kMaxRestart), g (kMaxRestart), 1 / rho, -kappa / rho];
+// Hraw columns j - 1 (final) and j (c, c_j; subdiagonal follows next step);
+// the Givens rotation of the now final column j - 1 (estimate after j steps).
+__global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* __restrict__ dots,
+                                                  double2* __restrict__ Hraw, const double* __restrict__ tnorm,
+                                                  double2* __restrict__ coef, double2* __restrict__ H,
+                                                  double* __restrict__ cs, double2* __restrict__ sn,
+                                                  double2* __restrict__ g, double beta, double bnorm,
+                                                  double* __restrict__ est) {
+  static_assert(kMaxRestart <= 64, "one lane per Hessenberg row");
+  __shared__ double2 ss[kMaxRestart], rr[kMaxRestart], hs[kMaxRestart], col[kMaxRestart + 1], snl[kMaxRestart];
+  __shared__ double csl[kMaxRestart];
+  __shared__ double sh_rho;
+  __shared__ double2 sh_kappa;
+  const int t = threadIdx.x, q = j, ld = m + 1;
+  const double2 zero = make_double2(0.0, 0.0);
+  const double2 st = t < q ? dots[t] : zero, rt = t < q ? dots[q + t] : zero;
+  if (t < q) {
+    ss[t] = st;
+    rr[t] = rt;
+  }
+  // |s|^2 and s^H r over the wavefront
+  const double s2 = wave_sum(st.x * st.x + st.y * st.y);
+  const double2 sr = make_double2(wave_sum(st.x * rt.x + st.y * rt.y), wave_sum(st.x * rt.y - st.y * rt.x));
+  const double rho2 = dots[2 * q].x - s2;
+  const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+  const double ir = rho > 0.0 ? 1.0 / rho : 0.0;
+  double hsubj = 0.0;      // final H(j, j-1)
+  if (j >= 1) {
+    // column j - 1 becomes h + ||t|| s with subdiagonal ||t|| rho (kept in LDS for the rotations)
+    const double tn = tnorm[0];
+    double2* hc = Hraw + (int64_t)(j - 1) * ld;
+    if (t < j) {
+      const double2 c = rfma(tn, st, hc[t]);
+      hc[t] = c;
+      col[t] = c;
+    }
+    hsubj = tn * rho;
+    if (t == 0) hc[j] = make_double2(hsubj, 0.0);
+    if (t < j - 1) {
+      csl[t] = cs[t];
+      snl[t] = sn[t];
+    }
+  }
+  __syncthreads();
+  // H s over the j x j leading block (column k has rows <= k + 1)
+  if (t < q) {
+    double2 acc = zero;
+    for (int k = t > 0 ? t - 1 : 0; k < q; ++k) acc = cfma(Hraw[(int64_t)k * ld + t], ss[k], acc);
+    hs[t] = acc;
+  }
+  if (t == 0 && j >= 1) {
+    // Givens rotations of the now final column j - 1 (earlier rotations, then its own),
+    // the running entry kept in registers
+    const int jj = j - 1;
+    if (jj == 0) {
+      for (int i = 0; i <= m; ++i) g[i] = zero;
+      g[0] = make_double2(beta, 0.0);
+    }
+    double2 run = col[0];
+    for (int i = 0; i < jj; ++i) {
+      const double c = csl[i];
+      const double2 sv = snl[i], b = col[i + 1];
+      H[i * m + jj] = cadd(make_double2(c * run.x, c * run.y), cmul(sv, b));
+      const double2 sc = make_double2(sv.x, -sv.y);
+      run = csub(make_double2(c * b.x, c * b.y), cmul(sc, run));
+    }
+    const double aa = sqrt(run.x * run.x + run.y * run.y);
+    double c;
+    double2 sv, rr2;
+    if (hsubj == 0.0) {
+      c = 1.0; sv = zero; rr2 = run;
+    } else if (aa == 0.0) {
+      c = 0.0; sv = make_double2(1.0, 0.0); rr2 = make_double2(hsubj, 0.0);
+    } else {
+      const double tt = hypot(aa, hsubj);
+      c = aa / tt;
+      const double2 ph = make_double2(run.x / aa, run.y / aa);
+      sv = make_double2(ph.x * hsubj / tt, ph.y * hsubj / tt);
+      rr2 = make_double2(ph.x * tt, ph.y * tt);
+    }
+    cs[jj] = c;
+    sn[jj] = sv;
+    H[jj * m + jj] = rr2;
+    const double2 gj = g[jj];
+    const double2 ng = cmul(make_double2(sv.x, -sv.y), gj);
+    g[jj + 1] = make_double2(-ng.x, -ng.y);
+    g[jj] = make_double2(c * gj.x, c * gj.y);
+    est[jj] = sqrt(ng.x * ng.x + ng.y * ng.y) / bnorm;
+  }
+  if (t == 0) {
+    const double2 hsub = j >= 1 ? make_double2(hsubj * ss[j - 1].x, hsubj * ss[j - 1].y) : zero;
+    const double2 vw = csub(dots[2 * q + 1], sr);
+    const double2 cj = make_double2((vw.x * ir - hsub.x) * ir, (vw.y * ir - hsub.y) * ir);
+    const double2 kappa = make_double2(hsub.x * ir + cj.x, hsub.y * ir + cj.y);
+    Hraw[(int64_t)j * ld + j] = cj;
+    sh_kappa = kappa;
+    coef[2 * kMaxRestart] = make_double2(ir, 0.0);
+    coef[2 * kMaxRestart + 1] = make_double2(-kappa.x * ir, -kappa.y * ir);
+  }
+  __syncthreads();
+  if (t < q) {
+    const double2 kappa = sh_kappa;
+    const double2 c = make_double2((rr[t].x - hs[t].x) * ir, (rr[t].y - hs[t].y) * ir);
+    Hraw[(int64_t)j * ld + t] = c;
+    const double2 ks = cmul(kappa, ss[t]);
+    coef[t] = ss[t];
+    coef[kMaxRestart + t] = make_double2(hs[t].x * ir + c.x - ks.x * ir, hs[t].y * ir + c.y - ks.y * ir);
+  }
+}
+
+// DCGS2 update, one read of V: v <- (v - V s) / rho (the finished basis
+// vector j, in place) and w <- w / rho - (kappa / rho) v - V g (the next
+// direction, in place), with rpart the per-block sums of |w|^2.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_dcgs_update(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+                                                          const double2* __restrict__ coef, T* __restrict__ v,
+                                                          T* __restrict__ w, double* __restrict__ rpart) {
+  __shared__ double2 cs_[kMaxRestart], cg_[kMaxRestart];
+  __shared__ double sh[4];
+  if (threadIdx.x < q) {
+    cs_[threadIdx.x] = coef[threadIdx.x];
+    cg_[threadIdx.x] = coef[kMaxRestart + threadIdx.x];
+  }
+  __syncthreads();
+  const double ir = coef[2 * kMaxRestart].x;
+  const double2 bv = coef[2 * kMaxRestart + 1];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 vi = ld2(v[i]), wi = ld2(w[i]);
+    double2 qa = make_double2(0.0, 0.0), ga = make_double2(0.0, 0.0);
+    for (int k = 0; k < q; ++k) {
+      const double2 x = ld2(V[(int64_t)k * ldv + i]);
+      qa = cfma(x, cs_[k], qa);
+      ga = cfma(x, cg_[k], ga);
+    }
+    v[i] = st2<T>(make_double2((vi.x - qa.x) * ir, (vi.y - qa.y) * ir));
+    const double2 bvi = cmul(bv, vi);
+    const T ws = st2<T>(make_double2(wi.x * ir + bvi.x - ga.x, wi.y * ir + bvi.y - ga.y));
+    w[i] = ws;
+    const double2 wr = ld2(ws);
+    acc = fma(wr.x, wr.x, fma(wr.y, wr.y, acc));
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) rpart[blockIdx.x] = acc;
 }
 
 // One right-hand side per workgroup z; per-system arrays at fixed strides,
@@ -1279,15 +1571,29 @@ void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* 
   k_wt<<<blocks_for(nv * kLanes), kThreads, 0, st>>>(nv, wtrowptr, wtcol, wtval, d0tau, x, t);
 }
 template <class T>
-void launch_spmv(int64_t n, int64_t ne, const int* rowptr, const int* col, const T* val, const int* wrowptr,
-                 const int* wcol, const double* wval, const double2* t, const T* x, const double2* b, T* y,
-                 hipStream_t st) {
-  k_spmv<T><<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, ne, rowptr, col, val, wrowptr, wcol, wval, t, x, b, y);
+void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, const T* sval, int64_t ne,
+                 const int* wrowptr, const int* wcol, const double* wval, const double2* t, const T* x,
+                 const double2* b, T* y, hipStream_t st, int grid, int schedule) {
+  const unsigned full = blocks_for(ns * kSellC);
+  unsigned g = grid > 0 && (unsigned)grid < full ? (unsigned)grid : full;
+  if (schedule && g < (unsigned)kXcds) schedule = 0;
+  k_spmv_sell<T><<<g, kThreads, 0, st>>>(ns, sptr, srow, scol, sval, x, b, y, schedule);
+  if (wrowptr)
+    k_gauge_add<T><<<blocks_for(ne * kLanes), kThreads, 0, st>>>(ne, wrowptr, wcol, wval, t, b ? -1.0 : 1.0, y);
+}
+int spmv_full_grid(int64_t ns) { return (int)blocks_for(ns * kSellC); }
+void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2* sval, float2* sval32,
+                        hipStream_t st) {
+  k_sell_gather<<<blocks_for(tot), kThreads, 0, st>>>(tot, src, val, sval, sval32);
 }
 template <class T>
 void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, const T* r, T* z,
                         hipStream_t st) {
   k_block_apply<T><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
+}
+int mdot2_parts(int64_t n) {
+  const int64_t tiles = (n + kDot2Rows - 1) / kDot2Rows;
+  return (int)(tiles < kDot2MaxBlocks ? (tiles > 0 ? tiles : 1) : kDot2MaxBlocks);
 }
 int mdot_parts(int64_t n) { return (int)((n + 2 * kThreads - 1) / (2 * kThreads)); }
 template <class T>
@@ -1298,14 +1604,6 @@ void launch_mdot(int64_t n, const T* V, int64_t ldv, int q, const T* w, double2*
 }
 void launch_reduce_cols(int q, int nparts, const double2* partial, double2* out, hipStream_t st, const int* flag) {
   k_reduce_cols<<<q, kThreads, 0, st>>>(partial, nparts, out, flag, 0, 0, nullptr);
-}
-void launch_reorth_decide(int q, const double2* h1, const double* nrm1, double2* h2, double* nrm, int* flag,
-                          int* counter, hipStream_t st) {
-  k_reorth_decide<<<1, 64, 0, st>>>(q, h1, nrm1, h2, nrm, flag, counter, 0, nullptr);
-}
-template <class T>
-void launch_update(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, hipStream_t st) {
-  k_update<T><<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, h, w);
 }
 template <class T>
 void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipStream_t st) {
@@ -1329,10 +1627,21 @@ void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
   k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x, 0, 0, nullptr);
 }
 template <class T>
-void launch_update_norm(int64_t n, const T* V, int64_t ldv, int q, const double2* h, T* w, double* rpart,
-                        double* out_norm, hipStream_t st, const int* flag) {
-  k_update_norm<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart, flag, 0, 0, 0, nullptr);
-  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, flag, nullptr);
+void launch_mdot2(int64_t n, const T* V, int64_t ldv, int q, const T* v, const T* w, double2* partial,
+                  hipStream_t st) {
+  dim3 grid(mdot2_parts(n), q > 0 ? (q + 7) / 8 : 1);
+  k_mdot2<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial);
+}
+void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
+                      double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
+                      hipStream_t st) {
+  k_dcgs_coef<<<1, 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, beta, bnorm, est);
+}
+template <class T>
+void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,
+                        double* out_norm, hipStream_t st) {
+  k_dcgs_update<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart);
+  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, nullptr, nullptr);
 }
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st) {
@@ -1431,21 +1740,27 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   k_to_c64<<<blocks_for(n), kThreads, 0, st>>>(n, in, out);
 }
 #define EDDY_INST(T)                                                                                              \
-  template void launch_spmv<T>(int64_t, int64_t, const int*, const int*, const T*, const int*, const int*,        \
-                               const double*, const double2*, const T*, const double2*, T*, hipStream_t);         \
+  template void launch_spmv<T>(int64_t, const int*, const int*, const int*, const T*, int64_t, const int*,       \
+                               const int*, const double*, const double2*, const T*, const double2*, T*,          \
+                               hipStream_t, int, int);                                                           \
   template void launch_block_apply<T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t);      \
   template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t, int, const int*); \
-  template void launch_update<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);               \
   template void launch_norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                \
   template void launch_scale_by_inv<T>(int64_t, const T*, const double*, T*, hipStream_t);                        \
   template void launch_scale_host<double2, T>(int64_t, const double2*, double, T*, hipStream_t);                  \
   template void launch_combine<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);              \
-  template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);                                        \
-  template void launch_update_norm<T>(int64_t, const T*, int64_t, int, const double2*, T*, double*, double*,      \
-                                      hipStream_t, const int*);
+  template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);
 EDDY_INST(double2)
 EDDY_INST(float2)
 #undef EDDY_INST
+template void launch_mdot2<double2>(int64_t, const double2*, int64_t, int, const double2*, const double2*, double2*,
+                                    hipStream_t);
+template void launch_mdot2<float2>(int64_t, const float2*, int64_t, int, const float2*, const float2*, double2*,
+                                   hipStream_t);
+template void launch_dcgs_update<double2>(int64_t, const double2*, int64_t, int, const double2*, double2*, double2*,
+                                          double*, double*, hipStream_t);
+template void launch_dcgs_update<float2>(int64_t, const float2*, int64_t, int, const double2*, float2*, float2*,
+                                         double*, double*, hipStream_t);
 #define EDDY_INST_B(T)                                                                                            \
   template void launch_block_apply_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, int64_t, \
                                         T*, const int*, hipStream_t);                                             \

@@ -117,6 +117,58 @@ int find_root(std::vector<int32_t>& p, int32_t x) {
 
 }  // namespace
 
+// Sliced ELL layout of the CSR pattern (see internal.h).  Sorting by length
+// inside a window keeps the padding small (rows of an edge matrix have a few
+// distinct lengths) while the row permutation stays local.
+eddy_status build_sell(eddy_mesh* m) {
+  const int64_t n = m->ndof();
+  const int64_t ns = (n + kSellC - 1) / kSellC;
+  std::vector<int32_t> order(ns * kSellC, -1);
+  for (int64_t w0 = 0; w0 < n; w0 += kSellWindow) {
+    const int64_t w1 = std::min<int64_t>(n, w0 + kSellWindow);
+    std::iota(order.begin() + w0, order.begin() + w1, (int32_t)w0);
+    std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int32_t a, int32_t b) {
+      return m->rowptr[a + 1] - m->rowptr[a] > m->rowptr[b + 1] - m->rowptr[b];
+    });
+  }
+  m->sell_ptr.assign(ns + 1, 0);
+  for (int64_t s = 0; s < ns; ++s) {
+    int32_t w = 0;
+    for (int l = 0; l < kSellC; ++l) {
+      const int32_t r = order[s * kSellC + l];
+      if (r >= 0) w = std::max(w, m->rowptr[r + 1] - m->rowptr[r]);
+    }
+    if ((int64_t)m->sell_ptr[s] + (int64_t)w * kSellC >= (int64_t)INT32_MAX) {
+      set_error("matrix too large for 32-bit sliced-ELL offsets");
+      return EDDY_ERR_ARG;
+    }
+    m->sell_ptr[s + 1] = m->sell_ptr[s] + w * kSellC;
+  }
+  const int64_t tot = m->sell_ptr[ns];
+  m->sell_row = order;
+  m->sell_col.assign(tot, 0);
+  m->sell_src.assign(tot, -1);
+  parallel_chunks(ns, [&](int, int64_t s0, int64_t s1) {
+    for (int64_t s = s0; s < s1; ++s) {
+      const int32_t w = (m->sell_ptr[s + 1] - m->sell_ptr[s]) / kSellC;
+      for (int l = 0; l < kSellC; ++l) {
+        const int32_t r = order[s * kSellC + l];
+        const int32_t len = r >= 0 ? m->rowptr[r + 1] - m->rowptr[r] : 0;
+        for (int32_t j = 0; j < w; ++j) {
+          const int64_t q = m->sell_ptr[s] + (int64_t)j * kSellC + l;
+          if (j < len) {
+            m->sell_src[q] = m->rowptr[r] + j;
+            m->sell_col[q] = m->col[m->rowptr[r] + j];
+          } else {
+            m->sell_col[q] = r >= 0 ? r : 0;
+          }
+        }
+      }
+    }
+  });
+  return EDDY_OK;
+}
+
 eddy_status build_mesh(eddy_mesh* m) {
   const int64_t nv = m->nv, nt = m->nt;
   const int32_t* T = m->tet.data();
@@ -282,6 +334,7 @@ eddy_status build_mesh(eddy_mesh* m) {
       if (m->col[p] == r) m->diagpos[r] = p;
   for (int64_t r = 0; r < ne + nc; ++r)
     if (m->diagpos[r] < 0) { set_error("row without a diagonal entry"); return EDDY_ERR_MESH; }
+  if (eddy_status st = build_sell(m); st != EDDY_OK) return st;
   // ---- W pattern + scatter lists
   auto genW = [&](int64_t r, std::vector<std::pair<int32_t, int32_t>>& out) {
     for (int32_t p = eptr[r]; p < eptr[r + 1]; ++p) {

@@ -30,6 +30,13 @@ class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int32)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("spmv_grid_full", C.c_int32), ("spmv_grid_c128", C.c_int32), ("spmv_grid_c64", C.c_int32),
+                ("spmv_sched_c128", C.c_int32), ("spmv_sched_c64", C.c_int32),
+                ("spmv_us_c128", C.c_float), ("spmv_us_c64", C.c_float),
+                ("spmv_us_sched_c128", C.c_float * 2), ("spmv_us_sched_c64", C.c_float * 2)]
+
+
 class _Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("relres", C.c_double), ("est_relres", C.c_double),
@@ -42,7 +49,7 @@ EXPORTS = [
     "eddy_mesh_conductor_nodes", "eddy_mesh_blocks", "eddy_op_workspace_bytes", "eddy_op_create",
     "eddy_op_destroy", "eddy_op_assemble", "eddy_rhs_from_current", "eddy_solve_workspace_bytes",
     "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched", "eddy_impedance", "eddy_delta_z_volume",
-    "eddy_ect_signals", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile",
+    "eddy_ect_signals", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile", "eddy_op_tuning",
     "eddy_status_string", "eddy_last_error",
 ]
 
@@ -76,6 +83,7 @@ def _load():
         "eddy_precond_apply": [VP, VP, VP, VP],
         "eddy_export": [VP, P(I32), P(I32), P(D), P(I32), P(I32), P(D), P(D), P(D), VP],
         "eddy_profile": [VP, I32, P(D), P(I64)],
+        "eddy_op_tuning": [VP, P(_Tuning)],
         "eddy_status_string": [I32],
         "eddy_last_error": [],
     }
@@ -344,6 +352,16 @@ class Operator:
         cnt = np.zeros(4, np.int64)
         _check(_lib.eddy_profile(self._h, int(enable), _ptr(ms, C.c_double), _ptr(cnt, C.c_int64)), "eddy_profile")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PROFILE_CLASSES)}
+
+    def tuning(self) -> dict:
+        """Launch shapes the autotuner chose at the first assemble (eddy_op_tuning)."""
+        t = _Tuning()
+        _check(_lib.eddy_op_tuning(self._h, C.byref(t)), "eddy_op_tuning")
+        out = {}
+        for f, _ in _Tuning._fields_:
+            v = getattr(t, f)
+            out[f] = list(v) if isinstance(v, C.Array) else v
+        return out
 
     def export(self):
         """Host copies of the stored arrays (see eddy_export)."""
