@@ -25,8 +25,8 @@ specification of the solver's learned variant.  Definitions:
   for l = 1, 2: H_{l+1} = relu(A_hat (H_l W_l) + b_l) + H_l;
   Y = A_hat (H_3 W3) + b3 (16 columns, the first two used): c_p = Y_p0 + i Y_p1.
 * Precision: every GEMM operand is rounded to bfloat16 (round to nearest
-  even) and accumulated in float32; biases, activations and the residual
-  path stay float32.  The oracle rounds at the same points and accumulates
+  even), in the backward pass too (dY, dZ, dT), and accumulated in float32;
+  biases, activations, the residual path and the loss stay float32.  The oracle rounds at the same points and accumulates
   in float64.  Backward passes treat the rounding as the identity.
 * Adam (Kingma and Ba, 2015) on float32 master weights; the bfloat16 copies
   are the rounded masters.
@@ -129,18 +129,18 @@ def loss_and_grad(theta: np.ndarray, ahat: np.ndarray, X: np.ndarray, cstar: np.
     g = {}
     # output layer: Y = Ab T3 + b3, T3 = bf16(Hb3 W3)
     g["b3"] = dY.sum(axis=0)
-    dT = bf16(Ab.T @ dY)
+    dT = bf16(Ab.T @ bf16(dY))
     g["W3"] = Hb[3].T @ dT
     dH = dT @ bf16(p["W3"]).T
     for l in (2, 1):
         dZ = dH * (Z[l] > 0)
         g[f"b{l}"] = dZ.sum(axis=0)
-        dT = bf16(Ab.T @ dZ)
+        dT = bf16(Ab.T @ bf16(dZ))
         g[f"W{l}"] = Hb[l].T @ dT
         dH = dH + dT @ bf16(p[f"W{l}"]).T
     dZ = dH * (Z[0] > 0)
     g["b0"] = dZ.sum(axis=0)
-    dT = bf16(Ab.T @ dZ)
+    dT = bf16(Ab.T @ bf16(dZ))
     g["W0"] = Hb[0].T @ dT
     g["W3"][:, 2:] = 0.0
     g["b3"][2:] = 0.0
