@@ -75,6 +75,10 @@ typedef struct {
                        /* process (SpMV, block-Jacobi apply, CGS2, basis) runs in  */
                        /* complex64; cycle residual, Hessenberg least squares,     */
                        /* solution update and final residual stay FP64            */
+  const float* gnn_theta;  /* NULL: plain block-Jacobi.  Otherwise the device      */
+                           /* parameters (EDDY_GNN_PARAMS floats) of the learned    */
+                           /* coarse correction, applied inside flexible GMRES     */
+                           /* with fallback (see eddy_gnn_* below)                 */
 } eddy_solve_opts;
 
 typedef struct {
@@ -95,6 +99,9 @@ typedef struct {
                            /* Gram-Schmidt pass: every step in eddy_solve (delayed */
                            /* scheme); in eddy_solve_batched, the steps where the  */
                            /* norm dropped below 1/sqrt(2) of ||w||                */
+  int32_t learned_cycles;  /* cycles run with the learned correction               */
+  int32_t fell_back;       /* 1 if the plain residual judged the learned cycles    */
+                           /* worse and the solve returned to plain block-Jacobi   */
 } eddy_solve_report;
 
 /* Launch shapes the operator picked by timing candidates on its own matrix
@@ -237,6 +244,57 @@ eddy_status eddy_delta_z_volume(const eddy_op* op_defect, int32_t nk, const eddy
  * already holds dZ (e.g. from eddy_delta_z_volume). */
 eddy_status eddy_ect_signals(int32_t npos, const eddy_c128* Z_defect, const eddy_c128* Z_free, eddy_c128* dZ,
                              eddy_c128* Z_FA, eddy_c128* Z_F3);
+
+/* ---- learned coarse correction --------------------------------------------
+ * A graph network on EDDY_GNN_SUBDOMAINS subdomains (the block-Jacobi blocks
+ * in bisection order, grouped into that many runs of equal block count; two
+ * subdomains are adjacent if a tetrahedron holds DOFs of both, i.e. the
+ * structural pattern of M couples them) predicts one complex
+ * coefficient c_p per subdomain; the preconditioned vector z = B r (B the
+ * block-Jacobi apply, equilibrated system) becomes z + sum_p c_p Z_p, Z_p = z
+ * on subdomain p.  Features per subdomain (EDDY_GNN_FEATURES floats, 8
+ * used): ||r_p|| / ||r|| sqrt(P), ||z_p|| / ||z|| sqrt(P), Re and Im of
+ * <z_p, r_p> / (||z_p|| ||r_p||), conductor-DOF fraction, log10(omega) / 6,
+ * log10(1 + sigma_p / 1e4) / 3 (sigma_p: subdomain mean over its DOFs of the
+ * largest conductivity of a tetrahedron containing the DOF), 1.  Network
+ * (float32 parameters, EDDY_GNN_PARAMS, order W0 [16x64], b0, W1 [64x64], b1,
+ * W2 [64x64], b2, W3 [64x16], b3 [16], row-major): T0 = X W0,
+ * H1 = relu(A T0 + b0), H_{l+1} = relu(A (H_l W_l) + b_l) + H_l (l = 1, 2),
+ * Y = A (H3 W3) + b3, c_p = Y_p0 + i Y_p1, A = D^-1/2 (adj + I) D^-1/2.
+ * Every GEMM operand is rounded to bfloat16 (MFMA, float32 accumulation).
+ * Training pair (r, e) with M e = r: c*_p = <Z_p, e - z> / ||Z_p||^2 minimises
+ * ||e - z'|| and loss = sum_p w_p |c_p - c*_p|^2, w_p = ||Z_p||^2 / ||e||^2,
+ * is the error energy the correction leaves above that minimum. */
+#define EDDY_GNN_SUBDOMAINS 64
+#define EDDY_GNN_FEATURES 16
+#define EDDY_GNN_OUTPUTS 16
+#define EDDY_GNN_PARAMS 10448
+
+/* Host: subdomain of every DOF (sub_of_dof[ndof]) and the 0/1 adjacency
+ * [P*P] for blocks of block_size DOFs.  Either pointer may be NULL. */
+eddy_status eddy_mesh_subdomains(const eddy_mesh* mesh, int32_t block_size, int32_t* sub_of_dof,
+                                 int32_t* adjacency);
+/* Host copy of the feature columns 4..7 [P*4] set at the last assembly. */
+eddy_status eddy_gnn_static_features(const eddy_op* op, float* static4);
+/* Device scratch (256-byte aligned) of eddy_gnn_forward / eddy_gnn_train_step for nsamp samples. */
+eddy_status eddy_gnn_scratch_bytes(int32_t nsamp, size_t* bytes);
+/* Features X [P*16] and, if xstar != NULL, targets cstar [P*2] (re, im) and
+ * weights w [P] (all float32, device) of the pair r = b - M x, e = x* - x of
+ * the physical system (b, x, xstar: device complex128 [ndof]); the network
+ * sees them in the equilibrated variables, where B acts.  Uses the
+ * operator's temporaries (not concurrently with another call on it). */
+eddy_status eddy_gnn_pair(const eddy_op* op, const eddy_c128* b, const eddy_c128* x, const eddy_c128* xstar,
+                          float* X, float* cstar, float* w, eddy_stream stream);
+/* Y [nsamp][P*16] = network(theta; X [nsamp][P*16]) (device float32). */
+eddy_status eddy_gnn_forward(const eddy_op* op, int32_t nsamp, const float* theta, const float* X, float* Y,
+                             void* scratch, size_t scratch_bytes, eddy_stream stream);
+/* One training step on a batch (device arrays): per-sample loss [nsamp],
+ * the batch-mean gradient grad_mean [EDDY_GNN_PARAMS] (may be NULL), then
+ * Adam (beta 0.9, 0.999, eps 1e-8, step >= 1 counting from 1) on theta, m, v
+ * unless lr == 0. */
+eddy_status eddy_gnn_train_step(const eddy_op* op, int32_t nsamp, float* theta, float* m, float* v, const float* X,
+                                const float* cstar, const float* w, int32_t step, float lr, float* loss,
+                                float* grad_mean, void* scratch, size_t scratch_bytes, eddy_stream stream);
 
 /* ---- building blocks (parity tests and benchmarks) ---------------------
  * y = M x with the gauge applied in factored form (unscaled system). */

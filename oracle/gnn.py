@@ -7,7 +7,9 @@ specification of the solver's learned variant.  Definitions:
 * Subdomains: the block-Jacobi blocks (recursive coordinate bisection, in
   their bisection order) grouped into P consecutive runs of equal block count,
   so each subdomain is a spatially compact union of blocks.  Two subdomains
-  are adjacent if M couples a DOF of one with a DOF of the other.
+  are adjacent if a tetrahedron holds DOFs of both (its six edges, and its
+  four nodes when it conducts): the structural coupling of M, whatever the
+  values.
   A_hat = D^-1/2 (A + I) D^-1/2 (symmetric normalisation with self loops).
 * Correction of a preconditioned residual z = B r (B the block-Jacobi apply):
   z' = z + sum_p c_p Z_p with Z_p = z restricted to subdomain p.  For a
@@ -168,10 +170,16 @@ def subdomains(blocks: list, nparts: int = P) -> np.ndarray:
     return sub
 
 
-def adjacency(M, sub: np.ndarray, nparts: int = P) -> np.ndarray:
-    Mc = M.tocoo()
+def adjacency(topo, tet: np.ndarray, sub: np.ndarray, nparts: int = P) -> np.ndarray:
+    """0/1 subdomain adjacency from the tetrahedra (module doc)."""
     a = np.zeros((nparts, nparts), dtype=np.int64)
-    a[sub[Mc.row], sub[Mc.col]] = 1
+    ne = topo.ne
+    for t in range(tet.shape[0]):
+        d = list(topo.tet2edge[t])
+        if topo.cond_tet[t]:
+            d += [ne + topo.vmap[v] for v in tet[t]]
+        ss = np.unique(sub[np.asarray(d)])
+        a[np.ix_(ss, ss)] = 1
     np.fill_diagonal(a, 0)
     return a
 

@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-SOURCES = [("mesh.cpp", False), ("api.cpp", False), ("kernels.hip", True)]
+SOURCES = [("mesh.cpp", False), ("api.cpp", False), ("kernels.hip", True), ("gnn.hip", True)]
 
 
 def _run(cmd):

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "gnn.h"
 #include "kernels.h"
 
 namespace eddy {
@@ -75,6 +76,17 @@ struct eddy_op {
   float2 *val32, *minv32;       // complex64 copies for the mixed-precision inner loop
   double2* sval;                // sliced ELL values (complex128 and complex64)
   float2* sval32;
+  // learned coarse correction: subdomain ranges in the block DOF list,
+  // normalised adjacency (bf16), static features, statistics and network
+  // buffers for one sample; host copies for the static features
+  int *sub_ptr;
+  uint16_t* ahat;
+  float *static4, *gnn_X, *gnn_Y, *gnn_scr;
+  double2 *gnn_part, *gnn_sums;
+  bool gnn_ok = false;
+  std::vector<int32_t> sub_of_dof_h, adj_h;
+  std::vector<uint32_t> regmask_h;
+  std::vector<float> static4_h;
   eddy_tuning tune = {};        // SpMV grid caps (autotuned at the first assembly)
   bool tuned = false;
   double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *d0taup, *lumped, *s, *nu_reg, *sig_reg;
@@ -163,7 +175,22 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->red = c.take<double2>(kRedBlocks * (kMaxRestart + 1));
   o->rred = c.take<double>(kRedBlocks + 8);
   o->status = c.take<int>(4);
+  o->sub_ptr = c.take<int>(kGnnP + 1);
+  o->ahat = c.take<uint16_t>(kGnnP * kGnnP);
+  o->static4 = c.take<float>(kGnnP * 4);
+  o->gnn_X = c.take<float>(kGnnP * kGnnFin);
+  o->gnn_Y = c.take<float>(kGnnP * kGnnFout);
+  o->gnn_scr = c.take<float>(kGnnScratch);
+  o->gnn_part = c.take<double2>(kGnnP * kGnnStatParts * 4);
+  o->gnn_sums = c.take<double2>(kGnnP * 4 + 4);
   return c.off + 256;
+}
+
+uint16_t host_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
 
 uint64_t geometry_hash(const eddy_mesh* m) {
@@ -397,6 +424,25 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   UP(o->sell_ptr, m->sell_ptr); UP(o->sell_row, m->sell_row); UP(o->sell_col, m->sell_col);
   UP(o->sell_src, m->sell_src);
 #undef UP
+  // subdomains of the learned correction (unavailable with more than 32 regions)
+  std::vector<int32_t> sub_ptr;
+  std::vector<uint16_t> ahat_h(kGnnP * kGnnP, 0);
+  if (r == EDDY_OK && m->nreg <= 32) {
+    r = build_subdomains(m, p->block_size, sub_ptr, o->sub_of_dof_h, o->adj_h, o->regmask_h);
+    if (r == EDDY_OK) {
+      std::vector<double> deg(kGnnP, 1.0);
+      for (int a = 0; a < kGnnP; ++a)
+        for (int c = 0; c < kGnnP; ++c) deg[a] += o->adj_h[a * kGnnP + c];
+      for (int a = 0; a < kGnnP; ++a)
+        for (int c = 0; c < kGnnP; ++c) {
+          const double v = (a == c || o->adj_h[a * kGnnP + c]) ? 1.0 / std::sqrt(deg[a] * deg[c]) : 0.0;
+          ahat_h[a * kGnnP + c] = host_bf16((float)v);
+        }
+      r = upload(o->sub_ptr, sub_ptr, s);
+      if (r == EDDY_OK) r = upload(o->ahat, ahat_h, s);
+      o->gnn_ok = r == EDDY_OK;
+    }
+  }
   if (r == EDDY_OK) {
     hipError_t e = hipStreamSynchronize(s);   // host vectors are freed after return
     if (e != hipSuccess) { set_error(hipGetErrorString(e)); r = EDDY_ERR_DEVICE; }
@@ -446,6 +492,29 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   HIP_TRY(hipStreamSynchronize(s));
   if (stat & 2) { set_error("zero diagonal entry in M"); return EDDY_ERR_SINGULAR_BLOCK; }
   if (stat & 1) { set_error("zero pivot in a block-Jacobi block"); return EDDY_ERR_SINGULAR_BLOCK; }
+  if (o->gnn_ok) {   // static features of the learned correction (depend on sigma and omega)
+    std::vector<double> cnt(kGnnP, 0.0), cond(kGnnP, 0.0), ssum(kGnnP, 0.0);
+    for (int64_t i = 0; i < o->n; ++i) {
+      const uint32_t mask = o->regmask_h[i];
+      double smax = 0.0;
+      for (int rr = 0; rr < o->nreg; ++rr)
+        if (mask & (1u << rr)) smax = std::max(smax, sigma[rr]);
+      const int p = o->sub_of_dof_h[i];
+      cnt[p] += 1.0;
+      if (i >= o->ne) cond[p] += 1.0;
+      ssum[p] += smax;
+    }
+    o->static4_h.assign(kGnnP * 4, 0.f);
+    for (int p = 0; p < kGnnP; ++p) {
+      const double c = std::max(cnt[p], 1.0);
+      o->static4_h[p * 4 + 0] = (float)(cond[p] / c);
+      o->static4_h[p * 4 + 1] = (float)(std::log10(omega) / 6.0);
+      o->static4_h[p * 4 + 2] = (float)(std::log10(1.0 + ssum[p] / c / 1e4) / 3.0);
+      o->static4_h[p * 4 + 3] = 1.f;
+    }
+    HIP_TRY(hipMemcpyAsync(o->static4, o->static4_h.data(), sizeof(float) * kGnnP * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   if (!o->tuned) {   // the pattern fixes the best launch shape: tune at the first assembly only
     eddy_tuning& t = o->tune;
     t.spmv_grid_full = (int32_t)spmv_full_grid(o->ns);
@@ -533,12 +602,24 @@ struct SolveWs {
   // coefficients, zeros, ||t|| of the pending direction
   double2 *Hraw, *dots, *coef, *zeros;
   double* tnorm;
+  // learned correction (flexible GMRES): preconditioned basis, network scratch
+  double2* Z;
+  float2* Z32;
+  float* gscr;
+  double2* Sall;     // per-step finishing transforms (s, rho) of a flexible cycle
+  double* rhoall;
 };
 inline int64_t basis_ld(int64_t n) { return (n + 63) / 64 * 64; }   // 512-B aligned basis vectors
 
-size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne, int precision) {
+size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne, int precision,
+                   bool learned = false) {
   Carve c(base);
   const bool mixed = precision == 1;
+  w->Z = c.take<double2>(learned && !mixed ? (int64_t)m * basis_ld(n) : 0);
+  w->Z32 = c.take<float2>(learned && mixed ? (int64_t)m * basis_ld(n) : 0);
+  w->gscr = c.take<float>(learned ? kGnnScratch : 0);
+  w->Sall = c.take<double2>(learned ? (int64_t)m * m : 0);
+  w->rhoall = c.take<double>(learned ? m : 0);
   w->V32 = c.take<float2>(mixed ? (int64_t)(m + 1) * basis_ld(n) : 0);
   w->w32 = c.take<float2>(mixed ? n : 0);
   w->z32 = c.take<float2>(mixed ? n : 0);
@@ -671,6 +752,7 @@ struct Inner {
   T* z;
   const T* sval;     // sliced ELL values
   const T* minv;
+  T* Z;              // preconditioned basis of the learned (flexible) cycles, or null
 };
 
 // Restarted right-preconditioned GMRES(m) with CGS2.  x~ (W.xt) starts at
@@ -695,7 +777,18 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
   const int nparts = mdot2_parts(n);
   const double2 zero2h[kMaxRestart + 2] = {};
   HIP_TRY(hipMemcpyAsync(W.zeros, zero2h, sizeof(zero2h), hipMemcpyHostToDevice, s));
+  // Learned correction: cycles 0..3 alternate plain (even) and learned (odd);
+  // the learned correction continues if its mean residual reduction per
+  // cycle is no worse than the plain one, and any later learned cycle more
+  // than 25% worse (in log reduction) than the plain mean returns the solve
+  // to plain block-Jacobi for good.
+  const float* theta = opts->gnn_theta;
+  int cyc = 0, n_plain = 0, n_learn = 0;
+  double lf_plain = 0.0, lf_learn = 0.0;
+  bool fell_back = false;
   while (true) {
+    const bool learned = theta && !fell_back && (cyc < 4 ? (cyc & 1) == 1 : true);
+    const double rel_start = beta / bnorm;
     // pending vector v_0 = r / beta; the DCGS2 step j finishes v_j and
     // projects the next direction once (see k_dcgs_coef)
     launch_scale_host(n, r, 1.0 / beta, I.V, s);
@@ -704,19 +797,28 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
     for (int j = 0; j < m; ++j) {
       T* vj = I.V + (int64_t)j * ld;
       hipEvent_t* ev = o->ev + 5 * ((j % kCheckEvery));
+      T* zj = learned ? I.Z + (int64_t)j * ld : I.z;
       if (o->profile) (void)hipEventRecord(ev[0], s);
-      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, vj, I.z, s);
+      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, vj, zj, s);
+      if (learned) {   // z_j += sum_p c_p (z_j on subdomain p), c from the network
+        launch_gnn_stats(o->blk_dofs, o->sub_ptr, (const T*)vj, (const T*)zj, (const T*)nullptr, (const T*)nullptr,
+                         nullptr, nullptr, o->gnn_part, o->gnn_sums, s);
+        launch_gnn_features(o->gnn_sums, o->static4, 0, o->gnn_X, nullptr, nullptr, s);
+        launch_gnn_forward(1, theta, o->ahat, o->gnn_X, o->gnn_Y, W.gscr, s);
+        launch_gnn_scale(o->blk_dofs, o->sub_ptr, o->gnn_Y, zj, s);
+      }
       if (o->profile) (void)hipEventRecord(ev[1], s);
-      if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, (const double2*)I.z, o->tvec, s);
+      if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, (const double2*)zj, o->tvec, s);
       if (o->profile) (void)hipEventRecord(ev[2], s);
       launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, I.sval, o->ne, gauge_op ? o->wrowptr : nullptr,
-                  o->wcol, o->wval, o->tvec, (const T*)I.z, nullptr, I.w, s,
+                  o->wcol, o->wval, o->tvec, (const T*)zj, nullptr, I.w, s,
                   std::is_same<T, float2>::value ? o->tune.spmv_grid_c64 : o->tune.spmv_grid_c128,
                   std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128);
       if (o->profile) (void)hipEventRecord(ev[3], s);
       launch_mdot2(n, (const T*)I.V, ld, j, (const T*)vj, (const T*)I.w, W.part, s);
       launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);
-      launch_dcgs_coef(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est, s);
+      launch_dcgs_coef(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est,
+                       learned ? W.Sall : nullptr, learned ? W.rhoall : nullptr, s);
       launch_dcgs_update(n, (const T*)I.V, ld, j, W.coef, vj, I.w, W.rpart, W.tnorm, s);
       launch_scale_by_inv(n, (const T*)I.w, W.tnorm, I.V + (int64_t)(j + 1) * ld, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
@@ -751,7 +853,10 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       for (int jj = jstart; jj < avail; ++jj) {
         if (!std::isfinite(est[jj])) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
         if (est[jj] <= opts->tol) {
-          if (est[jj] == 0.0) R.breakdown = 1;
+          // a zero estimate is a happy breakdown, except in a learned cycle,
+          // where the correction may have annihilated the direction: that only
+          // ends the cycle
+          if (est[jj] == 0.0 && !learned) R.breakdown = 1;
           k = jj + 1;
           it -= (j + 1) - k;    // steps after k were computed but are not used
           stop = true;
@@ -768,8 +873,13 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
     if (!stop) k = m;
     R.est_relres = est[k - 1];
     launch_backsolve(k, m, W.Hd, W.gd, W.yd, s);
-    launch_combine(n, (const T*)I.V, ld, k, W.yd, I.w, s);
-    launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, (const T*)I.w, I.z, s);
+    if (learned) {   // flexible update: x~ += Zt y, Zt the finished columns of the stored Z
+      launch_flex_coeffs(k, m, W.Sall, W.rhoall, W.yd, s);
+      launch_combine(n, (const T*)I.Z, ld, k, W.yd, I.z, s);
+    } else {
+      launch_combine(n, (const T*)I.V, ld, k, W.yd, I.w, s);
+      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, (const T*)I.w, I.z, s);
+    }
     launch_axpy(n, (const T*)I.z, W.xt, s);
     // FP64 true residual of the iterated operator: r = b~ - M~ x~
     op_spmv(o, W.xt, W.bt, W.w, o->tvec, s, gauge_op);
@@ -777,6 +887,23 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
     if ((st = read_norm(&beta)) != EDDY_OK) return st;
     R.restarts++;
     R.relres = beta / bnorm;
+    if (theta) {   // the plain residual judges the learned cycles
+      const double lf = std::log(std::max(R.relres, 1e-300) / std::max(rel_start, 1e-300)) / std::max(k, 1);
+      if (learned) {
+        ++R.learned_cycles;
+        lf_learn += lf;
+        ++n_learn;
+      } else if (!fell_back) {
+        lf_plain += lf;
+        ++n_plain;
+      }
+      if (!fell_back && n_plain > 0 && n_learn > 0) {
+        const double mp = lf_plain / n_plain, ml = lf_learn / n_learn;
+        if ((cyc == 3 && ml > mp) || (cyc > 3 && learned && lf > 0.8 * mp)) fell_back = true;
+      }
+      R.fell_back = fell_back ? 1 : 0;
+    }
+    ++cyc;
     if (R.relres <= opts->tol || it >= opts->max_iter) break;
     if (stop && R.breakdown) break;
     r = W.w;
@@ -793,7 +920,7 @@ eddy_status eddy_solve_workspace_bytes(const eddy_op* o, const eddy_solve_opts* 
   eddy_status st = check_opts(opts);
   if (st != EDDY_OK) return st;
   SolveWs w;
-  *bytes = carve_solve(&w, nullptr, o->n, opts->restart, o->nv, o->ne, opts->precision);
+  *bytes = carve_solve(&w, nullptr, o->n, opts->restart, o->nv, o->ne, opts->precision, opts->gnn_theta != nullptr);
   return EDDY_OK;
 }
 
@@ -807,12 +934,14 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   const int m = opts->restart;
   const int64_t n = o->n;
   SolveWs W;
-  const size_t need = carve_solve(&W, nullptr, n, m, o->nv, o->ne, opts->precision);
+  const bool learned = opts->gnn_theta != nullptr;
+  if (learned && !o->gnn_ok) { set_error("learned correction unavailable (more than 32 regions?)"); return EDDY_ERR_ARG; }
+  const size_t need = carve_solve(&W, nullptr, n, m, o->nv, o->ne, opts->precision, learned);
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) {
     set_error("solve workspace too small or misaligned: need " + std::to_string(need) + " bytes");
     return EDDY_ERR_WORKSPACE;
   }
-  carve_solve(&W, ws, n, m, o->nv, o->ne, opts->precision);
+  carve_solve(&W, ws, n, m, o->nv, o->ne, opts->precision, learned);
   hipStream_t s = (hipStream_t)stream;
   using cd = std::complex<double>;
   double hbuf[8];
@@ -857,10 +986,10 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   R.precision_used = mixed ? 1 : 0;
   if (bnorm > 0) {
     if (mixed) {
-      Inner<float2> I{W.V32, W.w32, W.z32, o->sval32, o->minv32};
+      Inner<float2> I{W.V32, W.w32, W.z32, o->sval32, o->minv32, W.Z32};
       st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
     } else {
-      Inner<double2> I{W.V, W.w, W.z, o->sval, o->minv};
+      Inner<double2> I{W.V, W.w, W.z, o->sval, o->minv, W.Z};
       st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
     }
     if (st != EDDY_OK) return st;
@@ -1191,6 +1320,107 @@ eddy_status eddy_op_tuning(const eddy_op* o, eddy_tuning* out) {
   if (!o || !out) { set_error("NULL argument"); return EDDY_ERR_ARG; }
   if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
   *out = o->tune;
+  return EDDY_OK;
+}
+
+eddy_status eddy_mesh_subdomains(const eddy_mesh* mc, int32_t block_size, int32_t* sub_of_dof, int32_t* adjacency) {
+  if (!mc) { set_error("NULL mesh"); return EDDY_ERR_ARG; }
+  if (block_size < 1 || block_size > kMaxBlock) { set_error("block_size must be in 1..64"); return EDDY_ERR_ARG; }
+  eddy_mesh* m = const_cast<eddy_mesh*>(mc);
+  std::vector<int32_t> sub_ptr, sub, adj;
+  std::vector<uint32_t> mask;
+  try {
+    eddy_status st = build_subdomains(m, block_size, sub_ptr, sub, adj, mask);
+    if (st != EDDY_OK) return st;
+  } catch (const std::exception& e) {
+    set_error(std::string("host failure: ") + e.what());
+    return EDDY_ERR_ARG;
+  }
+  if (sub_of_dof) std::memcpy(sub_of_dof, sub.data(), sizeof(int32_t) * sub.size());
+  if (adjacency) std::memcpy(adjacency, adj.data(), sizeof(int32_t) * adj.size());
+  return EDDY_OK;
+}
+
+eddy_status eddy_gnn_static_features(const eddy_op* o, float* static4) {
+  if (!o || !static4) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (!o->gnn_ok || o->static4_h.empty()) { set_error("learned correction unavailable or operator not assembled"); return EDDY_ERR_ARG; }
+  std::memcpy(static4, o->static4_h.data(), sizeof(float) * kGnnP * 4);
+  return EDDY_OK;
+}
+
+eddy_status eddy_gnn_scratch_bytes(int32_t nsamp, size_t* bytes) {
+  if (nsamp < 1 || !bytes) { set_error("bad argument"); return EDDY_ERR_ARG; }
+  *bytes = (size_t)nsamp * (size_t)(kGnnScratch + kGnnParams + 1) * sizeof(float) + 512;
+  return EDDY_OK;
+}
+
+namespace {
+struct GnnScratchView {
+  float *scr, *grads, *loss;
+};
+eddy_status gnn_scratch(void* base, size_t bytes, int32_t nsamp, GnnScratchView& v) {
+  size_t need = 0;
+  eddy_gnn_scratch_bytes(nsamp, &need);
+  if (!base || ((uintptr_t)base & 255) || bytes < need) {
+    set_error("scratch must be 256-byte aligned and at least eddy_gnn_scratch_bytes");
+    return EDDY_ERR_WORKSPACE;
+  }
+  v.scr = (float*)base;
+  v.grads = v.scr + (size_t)nsamp * kGnnScratch;
+  v.loss = v.grads + (size_t)nsamp * kGnnParams;
+  return EDDY_OK;
+}
+eddy_status gnn_check(const eddy_op* o) {
+  if (!o) { set_error("NULL operator"); return EDDY_ERR_ARG; }
+  if (!o->gnn_ok) { set_error("learned correction unavailable (more than 32 regions?)"); return EDDY_ERR_ARG; }
+  if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+  return EDDY_OK;
+}
+}  // namespace
+
+eddy_status eddy_gnn_pair(const eddy_op* oc, const eddy_c128* b, const eddy_c128* x, const eddy_c128* xstar,
+                          float* X, float* cstar, float* w, eddy_stream stream) {
+  if (eddy_status st = gnn_check(oc); st != EDDY_OK) return st;
+  if (!b || !x || !X || (xstar && (!cstar || !w))) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  eddy_op* o = const_cast<eddy_op*>(oc);
+  hipStream_t s = (hipStream_t)stream;
+  // equilibrated variables: r~ = s (b - M x) = s b - M~ (x / s), e~ = (x* - x) / s, z~ = B~ r~
+  launch_diag_scale(o->n, (const double2*)x, o->s, 1, o->tmp1, s);
+  op_spmv(o, o->tmp1, nullptr, o->tmp2, o->tvec, s, true);
+  launch_scaled_residual(o->n, (const double2*)b, o->s, o->tmp2, o->tmp1, s);
+  launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, o->minv, (const double2*)o->tmp1, o->tmp2, s);
+  launch_gnn_stats(o->blk_dofs, o->sub_ptr, (const double2*)o->tmp1, (const double2*)o->tmp2,
+                   (const double2*)xstar, xstar ? (const double2*)x : nullptr, nullptr, o->s, o->gnn_part,
+                   o->gnn_sums, s);
+  launch_gnn_features(o->gnn_sums, o->static4, xstar ? 1 : 0, X, cstar, w, s);
+  HIP_TRY(hipGetLastError());
+  return EDDY_OK;
+}
+
+eddy_status eddy_gnn_forward(const eddy_op* o, int32_t nsamp, const float* theta, const float* X, float* Y,
+                             void* scratch, size_t bytes, eddy_stream stream) {
+  if (eddy_status st = gnn_check(o); st != EDDY_OK) return st;
+  if (nsamp < 1 || !theta || !X || !Y) { set_error("bad argument"); return EDDY_ERR_ARG; }
+  GnnScratchView v;
+  if (eddy_status st = gnn_scratch(scratch, bytes, nsamp, v); st != EDDY_OK) return st;
+  launch_gnn_forward(nsamp, theta, o->ahat, X, Y, v.scr, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return EDDY_OK;
+}
+
+eddy_status eddy_gnn_train_step(const eddy_op* o, int32_t nsamp, float* theta, float* m, float* v, const float* X,
+                                const float* cstar, const float* w, int32_t step, float lr, float* loss,
+                                float* grad_mean, void* scratch, size_t bytes, eddy_stream stream) {
+  if (eddy_status st = gnn_check(o); st != EDDY_OK) return st;
+  if (nsamp < 1 || !theta || !m || !v || !X || !cstar || !w || !loss || step < 1 || !(lr >= 0)) {
+    set_error("bad argument");
+    return EDDY_ERR_ARG;
+  }
+  GnnScratchView sv;
+  if (eddy_status st = gnn_scratch(scratch, bytes, nsamp, sv); st != EDDY_OK) return st;
+  launch_gnn_train(nsamp, theta, m, v, o->ahat, X, cstar, w, sv.scr, sv.grads, loss, grad_mean, step, lr,
+                   (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
   return EDDY_OK;
 }
 

@@ -29,6 +29,28 @@ constexpr int kMaxRestart = 64;
 constexpr int kMaxWRow = 32;       // max nodes adjacent to one edge (LDS-staged gauge blocks)
 constexpr int kBatchChunk = 8;     // systems per pass of the batched SpMV / block-Jacobi kernels
 constexpr int kMaxDzCols = 4;
+// Learned coarse correction: a graph network on kGnnP subdomains, kGnnFin
+// input features, width kGnnWidth, kGnnFout outputs (the first two used).
+// Parameters (float32, in this order, row-major): W0 [Fin x W], b0 [W],
+// W1 [W x W], b1, W2 [W x W], b2, W3 [W x Fout], b3 [Fout].
+constexpr int kGnnP = 64;
+constexpr int kGnnFin = 16;
+constexpr int kGnnWidth = 64;
+constexpr int kGnnFout = 16;
+constexpr int kGnnOffW0 = 0;
+constexpr int kGnnOffB0 = kGnnOffW0 + kGnnFin * kGnnWidth;
+constexpr int kGnnOffW1 = kGnnOffB0 + kGnnWidth;
+constexpr int kGnnOffB1 = kGnnOffW1 + kGnnWidth * kGnnWidth;
+constexpr int kGnnOffW2 = kGnnOffB1 + kGnnWidth;
+constexpr int kGnnOffB2 = kGnnOffW2 + kGnnWidth * kGnnWidth;
+constexpr int kGnnOffW3 = kGnnOffB2 + kGnnWidth;
+constexpr int kGnnOffB3 = kGnnOffW3 + kGnnWidth * kGnnFout;
+constexpr int kGnnParams = kGnnOffB3 + kGnnFout;
+// per-sample scratch of the network kernels (float32 words): 7 float32
+// [P x W] arrays, Y [P x Fout], and bf16 arrays (2 per word): Xb [P x Fin],
+// 6 of [P x W], dYb [P x Fout]
+constexpr int kGnnScratch = 7 * kGnnP * kGnnWidth + kGnnP * kGnnFout +
+                            (kGnnP * kGnnFin + 6 * kGnnP * kGnnWidth + kGnnP * kGnnFout) / 2;
 // Sliced ELL copy of M for the SpMV: slices of kSellC rows (one wavefront,
 // one lane per row), rows sorted by decreasing length inside windows of
 // kSellWindow rows; slice s holds its width x kSellC entries column-major.
@@ -90,4 +112,12 @@ struct eddy_mesh {
 namespace eddy {
 eddy_status build_mesh(eddy_mesh* m);                  // topology + patterns + maps
 eddy_status build_blocks(eddy_mesh* m, int32_t b);     // RCB partition (cached)
+// Subdomains of the learned correction: the blocks of size b (bisection
+// order) grouped into kGnnP runs of equal block count.  sub_ptr[kGnnP + 1]:
+// ranges in the block DOF list; sub_of_dof[ndof]; adj[kGnnP * kGnnP]: 1 where
+// M couples two different subdomains; regmask[ndof]: bit r set if a
+// tetrahedron of region r contains the DOF (edge, or conductor node).
+eddy_status build_subdomains(eddy_mesh* m, int32_t b, std::vector<int32_t>& sub_ptr,
+                             std::vector<int32_t>& sub_of_dof, std::vector<int32_t>& adj,
+                             std::vector<uint32_t>& regmask);
 }  // namespace eddy

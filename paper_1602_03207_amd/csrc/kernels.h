@@ -123,9 +123,14 @@ int mdot2_parts(int64_t n);
 template <class T>
 void launch_mdot2(int64_t n, const T* V, int64_t ldv, int q, const T* v, const T* w, double2* partial,
                   hipStream_t st);
+// Sall [m x m] / rhoall [m] (may be null) record each step's finishing
+// transform (s, rho) for flexible cycles; launch_flex_coeffs then maps the
+// least-squares coefficients on the finished preconditioned columns to the
+// stored ones.
 void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
                       double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
-                      hipStream_t st);
+                      double2* Sall, double* rhoall, hipStream_t st);
+void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall, double2* y, hipStream_t st);
 template <class T>
 void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,
                         double* out_norm, hipStream_t st);

@@ -1032,7 +1032,8 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* _
                                                   double2* __restrict__ coef, double2* __restrict__ H,
                                                   double* __restrict__ cs, double2* __restrict__ sn,
                                                   double2* __restrict__ g, double beta, double bnorm,
-                                                  double* __restrict__ est) {
+                                                  double* __restrict__ est, double2* __restrict__ Sall,
+                                                  double* __restrict__ rhoall) {
   static_assert(kMaxRestart <= 64, "one lane per Hessenberg row");
   __shared__ double2 ss[kMaxRestart], rr[kMaxRestart], hs[kMaxRestart], col[kMaxRestart + 1], snl[kMaxRestart];
   __shared__ double csl[kMaxRestart];
@@ -1051,6 +1052,10 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* _
   const double rho2 = dots[2 * q].x - s2;
   const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
   const double ir = rho > 0.0 ? 1.0 / rho : 0.0;
+  if (Sall) {   // the finishing transform of step j, for flexible cycles
+    if (t < q) Sall[(int64_t)j * m + t] = st;
+    if (t == 0) rhoall[j] = rho;
+  }
   double hsubj = 0.0;      // final H(j, j-1)
   if (j >= 1) {
     // column j - 1 becomes h + ||t|| s with subdiagonal ||t|| rho (kept in LDS for the rotations)
@@ -1192,7 +1197,8 @@ __device__ void backsolve_body(int k, int m, const double2* __restrict__ H, cons
     for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(H[i * m + l], y[l]));
     const double2 d = H[i * m + i];
     const double den = d.x * d.x + d.y * d.y;
-    y[i] = cmul(acc, make_double2(d.x / den, -d.y / den));
+    // a zero pivot (a direction the preconditioner annihilated) contributes nothing
+    y[i] = den > 0.0 ? cmul(acc, make_double2(d.x / den, -d.y / den)) : make_double2(0.0, 0.0);
   }
 }
 
@@ -1634,8 +1640,25 @@ void launch_mdot2(int64_t n, const T* V, int64_t ldv, int q, const T* v, const T
 }
 void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
                       double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
-                      hipStream_t st) {
-  k_dcgs_coef<<<1, 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, beta, bnorm, est);
+                      double2* Sall, double* rhoall, hipStream_t st) {
+  k_dcgs_coef<<<1, 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, beta, bnorm, est, Sall, rhoall);
+}
+// Flexible cycles: the basis vector q_j = (v_j - sum_{i<j} s_i^(j) q_i) / rho_j
+// was finished after z_j = B_j v_j was formed, so the columns matching the
+// Hessenberg matrix are Zt_j = (Z_j - sum_{i<j} s_i^(j) Zt_i) / rho_j.  Turn
+// the coefficients y on Zt (k of them) into coefficients on the stored Z.
+__global__ void k_flex_coeffs(int k, int m, const double2* __restrict__ Sall, const double* __restrict__ rhoall,
+                              double2* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int jj = k - 1; jj >= 0; --jj) {
+    const double r = rhoall[jj];
+    const double2 u = r > 0.0 ? make_double2(y[jj].x / r, y[jj].y / r) : make_double2(0.0, 0.0);
+    y[jj] = u;
+    for (int i = 0; i < jj; ++i) y[i] = csub(y[i], cmul(u, Sall[(int64_t)jj * m + i]));
+  }
+}
+void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall, double2* y, hipStream_t st) {
+  k_flex_coeffs<<<1, 64, 0, st>>>(k, m, Sall, rhoall, y);
 }
 template <class T>
 void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,

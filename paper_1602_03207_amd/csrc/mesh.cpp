@@ -434,4 +434,36 @@ eddy_status build_blocks(eddy_mesh* m, int32_t b) {
   return EDDY_OK;
 }
 
+eddy_status build_subdomains(eddy_mesh* m, int32_t b, std::vector<int32_t>& sub_ptr,
+                             std::vector<int32_t>& sub_of_dof, std::vector<int32_t>& adj,
+                             std::vector<uint32_t>& regmask) {
+  if (eddy_status st = build_blocks(m, b); st != EDDY_OK) return st;
+  if (m->nreg > 32) { set_error("the learned correction supports at most 32 regions"); return EDDY_ERR_ARG; }
+  const int64_t n = m->ndof(), nb = (int64_t)m->blk_ptr.size() - 1;
+  sub_ptr.assign(kGnnP + 1, 0);
+  sub_of_dof.assign(n, 0);
+  for (int p = 0; p <= kGnnP; ++p) {
+    const int64_t k0 = (p * nb + kGnnP - 1) / kGnnP;   // first block with floor(k P / nb) >= p
+    sub_ptr[p] = m->blk_ptr[std::min<int64_t>(k0, nb)];
+  }
+  for (int64_t k = 0; k < nb; ++k)
+    for (int32_t q = m->blk_ptr[k]; q < m->blk_ptr[k + 1]; ++q) sub_of_dof[m->blk_dofs[q]] = (int32_t)((k * kGnnP) / nb);
+  adj.assign(kGnnP * kGnnP, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int32_t p = m->rowptr[r]; p < m->rowptr[r + 1]; ++p) {
+      const int32_t a = sub_of_dof[r], c = sub_of_dof[m->col[p]];
+      if (a != c) adj[a * kGnnP + c] = 1;
+    }
+  regmask.assign(n, 0u);
+  for (int64_t t = 0; t < m->nt; ++t) {
+    const uint32_t bit = 1u << m->region[t];
+    for (int l = 0; l < 6; ++l) regmask[m->tet2edge[6 * t + l]] |= bit;
+    for (int k = 0; k < 4; ++k) {
+      const int32_t c = m->vmap[m->tet[4 * t + k]];
+      if (c >= 0) regmask[m->ne + c] |= bit;
+    }
+  }
+  return EDDY_OK;
+}
+
 }  // namespace eddy

@@ -27,7 +27,8 @@ class _Params(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int32),
+                ("gnn_theta", C.c_void_p)]
 
 
 class _Tuning(C.Structure):
@@ -41,7 +42,8 @@ class _Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("relres", C.c_double), ("est_relres", C.c_double),
                 ("seconds", C.c_double), ("gauge_in_operator", C.c_int32), ("cg_iters", C.c_int32),
-                ("div_residual", C.c_double), ("precision_used", C.c_int32), ("reorth_steps", C.c_int32)]
+                ("div_residual", C.c_double), ("precision_used", C.c_int32), ("reorth_steps", C.c_int32),
+                ("learned_cycles", C.c_int32), ("fell_back", C.c_int32)]
 
 
 EXPORTS = [
@@ -50,6 +52,8 @@ EXPORTS = [
     "eddy_op_destroy", "eddy_op_assemble", "eddy_rhs_from_current", "eddy_solve_workspace_bytes",
     "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched", "eddy_impedance", "eddy_delta_z_volume",
     "eddy_ect_signals", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile", "eddy_op_tuning",
+    "eddy_mesh_subdomains", "eddy_gnn_static_features", "eddy_gnn_scratch_bytes", "eddy_gnn_pair",
+    "eddy_gnn_forward", "eddy_gnn_train_step",
     "eddy_status_string", "eddy_last_error",
 ]
 
@@ -84,6 +88,12 @@ def _load():
         "eddy_export": [VP, P(I32), P(I32), P(D), P(I32), P(I32), P(D), P(D), P(D), VP],
         "eddy_profile": [VP, I32, P(D), P(I64)],
         "eddy_op_tuning": [VP, P(_Tuning)],
+        "eddy_mesh_subdomains": [VP, I32, P(I32), P(I32)],
+        "eddy_gnn_static_features": [VP, P(C.c_float)],
+        "eddy_gnn_scratch_bytes": [I32, P(C.c_size_t)],
+        "eddy_gnn_pair": [VP, VP, VP, VP, VP, VP, VP, VP],
+        "eddy_gnn_forward": [VP, I32, VP, VP, VP, VP, C.c_size_t, VP],
+        "eddy_gnn_train_step": [VP, I32, VP, VP, VP, VP, VP, VP, I32, C.c_float, VP, VP, VP, C.c_size_t, VP],
         "eddy_status_string": [I32],
         "eddy_last_error": [],
     }
@@ -119,6 +129,9 @@ def _stream():
 
 def _dev(t):
     return C.c_void_p(t.data_ptr())
+
+
+GNN_P, GNN_FIN, GNN_FOUT, GNN_PARAMS = 64, 16, 16, 10448
 
 
 def ect_signals(Z_defect, Z_free=None):
@@ -198,6 +211,14 @@ class Mesh:
             _check(_lib.eddy_mesh_conductor_nodes(self._h, _ptr(out, C.c_int32)), "eddy_mesh_conductor_nodes")
         return out
 
+    def subdomains(self, block_size: int):
+        """(sub_of_dof [ndof], adjacency [64, 64]) of the learned correction (eddy_mesh_subdomains)."""
+        sub = np.empty(self.ndof, np.int32)
+        adj = np.empty(GNN_P * GNN_P, np.int32)
+        _check(_lib.eddy_mesh_subdomains(self._h, block_size, _ptr(sub, C.c_int32), _ptr(adj, C.c_int32)),
+               "eddy_mesh_subdomains")
+        return sub, adj.reshape(GNN_P, GNN_P)
+
     def blocks(self, block_size: int):
         nb = C.c_int64()
         _check(_lib.eddy_mesh_blocks(self._h, block_size, C.byref(nb), None, None), "eddy_mesh_blocks")
@@ -228,6 +249,8 @@ class SolveReport:
     div_residual: float = 0.0
     precision_used: int = 0
     reorth_steps: int = 0
+    learned_cycles: int = 0
+    fell_back: bool = False
 
 
 def _aligned(nbytes: int, device):
@@ -282,9 +305,15 @@ class Operator:
         _check(_lib.eddy_rhs_from_current(self._h, _dev(J), _dev(b), _stream()), "eddy_rhs_from_current")
         return b
 
-    def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64"):
-        """precision: "fp64", or "mixed" (complex64 Krylov process, FP64 outer residual)."""
-        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1}[precision])
+    def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64", gnn_theta=None):
+        """precision: "fp64", or "mixed" (complex64 Krylov process, FP64 outer residual).
+        gnn_theta: float32 device tensor of EDDY_GNN_PARAMS network parameters
+        (the learned coarse correction with fallback), or None."""
+        if gnn_theta is not None:
+            assert gnn_theta.dtype.is_floating_point and gnn_theta.element_size() == 4 and gnn_theta.is_contiguous()
+            assert gnn_theta.numel() == GNN_PARAMS
+        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1}[precision],
+                     None if gnn_theta is None else gnn_theta.data_ptr())
         nbytes = C.c_size_t()
         _check(_lib.eddy_solve_workspace_bytes(self._h, C.byref(opts), C.byref(nbytes)), "eddy_solve_workspace_bytes")
         if self._solve_ws is None or self._solve_ws[2] < nbytes.value:
@@ -296,7 +325,8 @@ class Operator:
                                     C.byref(rep), _stream()), "eddy_solve")
         return x, SolveReport(rep.iters, rep.restarts, bool(rep.converged), bool(rep.breakdown), rep.relres,
                               rep.est_relres, rep.seconds, bool(rep.gauge_in_operator), rep.cg_iters,
-                              rep.div_residual, rep.precision_used, rep.reorth_steps)
+                              rep.div_residual, rep.precision_used, rep.reorth_steps, rep.learned_cycles,
+                              bool(rep.fell_back))
 
     def solve_batched(self, B, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64"):
         """B: complex128 device tensor [nrhs, ndof] -> (X [nrhs, ndof], [SolveReport])."""
@@ -352,6 +382,57 @@ class Operator:
         cnt = np.zeros(4, np.int64)
         _check(_lib.eddy_profile(self._h, int(enable), _ptr(ms, C.c_double), _ptr(cnt, C.c_int64)), "eddy_profile")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PROFILE_CLASSES)}
+
+    # ---- learned coarse correction (thin wrappers of eddy_gnn_*)
+    def gnn_static_features(self):
+        out = np.empty(GNN_P * 4, np.float32)
+        _check(_lib.eddy_gnn_static_features(self._h, _ptr(out, C.c_float)), "eddy_gnn_static_features")
+        return out.reshape(GNN_P, 4)
+
+    def _gnn_scratch(self, nsamp):
+        nb = C.c_size_t()
+        _check(_lib.eddy_gnn_scratch_bytes(nsamp, C.byref(nb)), "eddy_gnn_scratch_bytes")
+        key = ("gnn", nsamp)
+        cache = getattr(self, "_gnn_ws", None)
+        if cache is None or cache[0] != key:
+            buf, p = _aligned(nb.value, self.device)
+            self._gnn_ws = (key, buf, p, nb.value)
+        return self._gnn_ws[2], self._gnn_ws[3]
+
+    def gnn_pair(self, b, x, xstar=None):
+        """Features X [64, 16] and (with xstar) targets c* [64, 2], weights w [64]
+        of the pair r = b - M x, e = xstar - x (complex128 device vectors)."""
+        import torch
+        X = torch.empty((GNN_P, GNN_FIN), dtype=torch.float32, device=self.device)
+        cs = torch.empty((GNN_P, 2), dtype=torch.float32, device=self.device)
+        w = torch.empty(GNN_P, dtype=torch.float32, device=self.device)
+        t = xstar is not None
+        _check(_lib.eddy_gnn_pair(self._h, _dev(b), _dev(x), _dev(xstar) if t else None, _dev(X),
+                                  _dev(cs) if t else None, _dev(w) if t else None, _stream()), "eddy_gnn_pair")
+        return X, cs, w
+
+    def gnn_forward(self, theta, X):
+        """Y [nsamp, 64, 16] of the network for X [nsamp, 64, 16] (float32 device)."""
+        import torch
+        X = X.reshape(-1, GNN_P, GNN_FIN).contiguous()
+        Y = torch.empty((X.shape[0], GNN_P, GNN_FOUT), dtype=torch.float32, device=self.device)
+        p, nb = self._gnn_scratch(X.shape[0])
+        _check(_lib.eddy_gnn_forward(self._h, X.shape[0], _dev(theta), _dev(X), _dev(Y), p, nb, _stream()),
+               "eddy_gnn_forward")
+        return Y
+
+    def gnn_train_step(self, theta, m, v, X, cstar, w, step, lr, grad_out=None):
+        """One Adam step (in place on theta, m, v); returns per-sample losses."""
+        import torch
+        X = X.reshape(-1, GNN_P, GNN_FIN).contiguous()
+        ns = X.shape[0]
+        loss = torch.empty(ns, dtype=torch.float32, device=self.device)
+        p, nb = self._gnn_scratch(ns)
+        _check(_lib.eddy_gnn_train_step(self._h, ns, _dev(theta), _dev(m), _dev(v), _dev(X),
+                                        _dev(cstar.contiguous()), _dev(w.contiguous()), int(step), float(lr),
+                                        _dev(loss), None if grad_out is None else _dev(grad_out), p, nb,
+                                        _stream()), "eddy_gnn_train_step")
+        return loss
 
     def tuning(self) -> dict:
         """Launch shapes the autotuner chose at the first assemble (eddy_op_tuning)."""

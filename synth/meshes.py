@@ -284,3 +284,41 @@ def tube_materials(freq_hz: float, sigma_tube=1e6, sigma_plate=2e6, sigma_deposi
     nu = np.full(len(TUBE_REGIONS), 1.0 / (mu0 * mu_r))
     sigma = np.array([0.0, sigma_tube, sigma_plate, sigma_deposit])
     return nu, sigma, 2 * np.pi * freq_hz
+
+
+def perturbed_tube(seed: int, **kw):
+    """A tube of the family above with seeded defects, for training and
+    held-out evaluation of the learned correction: 1-3 deposit annuli
+    (thickness U(0.1, 0.5) mm on the tube's outer surface, length U(2, 10) mm,
+    centred in the scan zone) and, with probability 1/2, an axial crack in the
+    wall (width one azimuthal cell, depth U(10%, 80%) of the wall from the
+    outside, length U(2, 8) mm) whose tetrahedra become air.  Returns the mesh
+    and conductivity factors (tube, plate) drawn from U(0.7, 1.3).
+    """
+    rng = np.random.default_rng(seed)
+    p = dict(TUBE_DEFAULTS)
+    p.update(kw)
+    rt0, rt1 = p["r_tube"]
+    zs = p["scan_half"]
+    deps = []
+    for _ in range(int(rng.integers(1, 4))):
+        th = rng.uniform(0.1e-3, 0.5e-3)
+        ln = rng.uniform(2e-3, 10e-3)
+        zc = rng.uniform(-zs + ln / 2, zs - ln / 2)
+        deps.append((rt1, rt1 + th, zc - ln / 2, zc + ln / 2))
+    m = tube(deposits=deps, **kw)
+    if rng.random() < 0.5:
+        cen = m.xyz[m.tet].mean(axis=1)
+        r = np.hypot(cen[:, 0], cen[:, 1])
+        ang = np.arctan2(cen[:, 1], cen[:, 0])
+        a0 = rng.uniform(-np.pi, np.pi)
+        half_w = 0.5 * p["h_theta"] / rt1 + 1e-9
+        depth = rng.uniform(0.1, 0.8) * (rt1 - rt0)
+        ln = rng.uniform(2e-3, 8e-3)
+        zc = rng.uniform(-zs + ln / 2, zs - ln / 2)
+        dang = np.angle(np.exp(1j * (ang - a0)))
+        crack = (m.region == 1) & (np.abs(dang) < 2 * half_w) & (r > rt1 - depth) & (np.abs(cen[:, 2] - zc) < ln / 2)
+        m.region = np.where(crack, 0, m.region).astype(np.int32)
+        m.meta["crack"] = {"angle": float(a0), "depth": float(depth), "length": float(ln), "z": float(zc),
+                           "tets": int(crack.sum())}
+    return m, (float(rng.uniform(0.7, 1.3)), float(rng.uniform(0.7, 1.3)))

@@ -110,3 +110,28 @@ def test_ect_signals_host_call_matches_oracle():
     dZ2, fa2, f32 = eddy.ect_signals(dZ)
     assert np.array_equal(dZ2, dZ) and np.allclose(fa2, ofa, rtol=0, atol=1e-15)
     assert eddy.ect_signals(np.zeros((0, 2, 2)))[1].shape == (0,)
+
+
+@pytest.mark.parametrize("case", ["c1", "tube"])
+def test_subdomains_and_adjacency_match_oracle(case):
+    """Learned-correction subdomains (host) against the oracle's construction
+    from its own block partition and matrix pattern."""
+    import oracle.gnn as G
+    from oracle.assemble import assemble
+    from oracle.blocks import rcb_blocks, dof_coords
+    eddy = lib()
+    if case == "c1":
+        m, cond, nu, sig = cube(8), [1], [1.0, 1.0], [0.0, 1.0]
+    else:
+        m = tube(h_z=4e-3, h_z_end=20e-3, h_theta=3e-3, n_theta_max=24, h_wall=0.6e-3, h_coil=1.5e-3,
+                 h_core=3e-3, h_out=8e-3)
+        cond, nu, sig = [1, 2, 3], [1.0] * 4, [0.0, 1.0, 2.0, 0.5]
+    flags = [1 if r in cond else 0 for r in range(len(nu))]
+    M = eddy.Mesh(m.xyz, m.tet, m.region, flags)
+    sub, adj = M.subdomains(64)
+    s = assemble(m.xyz, m.tet, m.region, nu, sig, 1.0, conductor_regions=cond)
+    blocks = rcb_blocks(dof_coords(m.xyz, s.topo.edges, s.topo.cond_nodes), 64)
+    osub = G.subdomains(blocks)
+    assert np.array_equal(sub, osub)
+    assert np.array_equal(adj, G.adjacency(s.topo, np.asarray(m.tet), osub))
+    assert adj.sum() > 0 and np.array_equal(adj, adj.T)

@@ -1,0 +1,161 @@
+"""GPU parity of the learned coarse correction against oracle/gnn.py.
+
+Tolerances.  Both sides round every GEMM operand to bfloat16 at the same
+points; they differ in the accumulation (float32 MFMA sums in hardware order
+vs float64) and in the float32 vs float64 elementwise steps, so a rounding
+decision near a bfloat16 tie can flip (one bf16 ulp, 2^-8 relative) and
+propagate through the later layers.  Forward outputs are held to 1e-2
+normwise relative, per-sample losses to 1e-2, the batch gradient to 3e-2
+normwise relative (the backward pass rounds dY, dZ, dT too).  Features and
+targets come from float64 sums on both sides (1e-6).  Adam: the first step
+moves each weight by about lr sign(g); at least 97% of the weights must move
+like the oracle's to 1e-3 lr (the rest have gradients near zero, where the
+sign is rounding).
+"""
+import numpy as np
+import pytest
+
+from synth import cube, cube_current
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+import oracle.gnn as G  # noqa: E402
+
+STATE = {}
+
+
+def c1():
+    if "op" in STATE:
+        return STATE
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle.assemble import assemble
+    from oracle.blocks import rcb_blocks, dof_coords
+    from paper_1602_03207_amd import eddy
+    m = cube(8)
+    nu, sig, omega = np.array([1.0, 1.0]), np.array([0.0, 1.0]), 50.0
+    M = eddy.Mesh(m.xyz, m.tet, m.region, [0, 1])
+    op = eddy.Operator(M, tau=1.0, block_size=64)
+    op.assemble(nu, sig, omega)
+    s = assemble(m.xyz, m.tet, m.region, nu, sig, omega, tau=1.0, conductor_regions=[1])
+    blocks = rcb_blocks(dof_coords(m.xyz, s.topo.edges, s.topo.cond_nodes), 64)
+    sub = G.subdomains(blocks)
+    ahat = G.normalized_adjacency(G.adjacency(s.topo, np.asarray(m.tet), sub))
+    STATE.update(m=m, M=M, op=op, s=s, blocks=blocks, sub=sub, ahat=ahat, nu=nu, sig=sig, omega=omega)
+    return STATE
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _samples(rng, ns):
+    X = rng.normal(size=(ns, G.P, G.F_IN)) * 0.8
+    X[:, :, 8:] = 0.0
+    cs = rng.normal(size=(ns, G.P)) * 0.3 + 1j * rng.normal(size=(ns, G.P)) * 0.3
+    w = rng.random((ns, G.P))
+    w /= w.sum(axis=1, keepdims=True)
+    return X.astype(np.float32), cs, w.astype(np.float32)
+
+
+def test_forward_matches_oracle():
+    S = c1()
+    op = S["op"]
+    rng = np.random.default_rng(21)
+    th = G.init_params(5)
+    th[G.N_PARAMS - G.F_OUT:G.N_PARAMS - G.F_OUT + 2] = [0.3, -0.2]
+    X, _, _ = _samples(rng, 3)
+    Y = op.gnn_forward(_dev(th), _dev(X)).cpu().numpy()
+    for k in range(3):
+        Yo, _ = G.forward(th, S["ahat"], X[k].astype(np.float64))
+        assert np.linalg.norm(Y[k] - Yo) <= 1e-2 * np.linalg.norm(Yo), k
+        assert np.abs(Yo[:, 2:]).max() == 0.0 and np.abs(Y[k][:, 2:]).max() == 0.0
+
+
+def test_gradient_and_loss_match_oracle():
+    S = c1()
+    op = S["op"]
+    rng = np.random.default_rng(22)
+    th = G.init_params(6)
+    ns = 4
+    X, cs, w = _samples(rng, ns)
+    theta = _dev(th)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    g = torch.empty_like(theta)
+    c2 = np.stack([cs.real, cs.imag], axis=-1)
+    loss = op.gnn_train_step(theta, m, v, _dev(X), _dev(c2), _dev(w), 1, 0.0, grad_out=g).cpu().numpy()
+    assert np.array_equal(theta.cpu().numpy(), th.astype(np.float32))       # lr = 0: no update
+    go = np.zeros(G.N_PARAMS)
+    for k in range(ns):
+        lo, gk = G.loss_and_grad(th, S["ahat"], X[k].astype(np.float64), cs[k], w[k].astype(np.float64))
+        assert abs(loss[k] - lo) <= 1e-2 * lo, k
+        go += gk / ns
+    gg = g.cpu().numpy()
+    assert np.linalg.norm(gg - go) <= 3e-2 * np.linalg.norm(go)
+    # per block of parameters too
+    o = 0
+    for name, shp in G.PARAM_SHAPES:
+        nn = int(np.prod(shp))
+        if np.linalg.norm(go[o:o + nn]) > 0:
+            assert np.linalg.norm(gg[o:o + nn] - go[o:o + nn]) <= 5e-2 * np.linalg.norm(go[o:o + nn]), name
+        o += nn
+    # one Adam step against the oracle's
+    lr = 1e-2
+    op.gnn_train_step(theta, m, v, _dev(X), _dev(c2), _dev(w), 1, lr)
+    to, _, _ = G.adam(th, np.zeros_like(th), np.zeros_like(th), go, 1, lr)
+    d_gpu = theta.cpu().numpy().astype(np.float64) - th
+    d_or = to - th
+    live = np.abs(go) > 0
+    close = np.abs(d_gpu[live] - d_or[live]) <= 1e-3 * lr + 1e-6
+    assert close.mean() >= 0.97
+    assert np.abs(d_gpu).max() <= 1.01 * lr + 1e-6
+
+
+def test_pair_features_and_targets_match_oracle():
+    S = c1()
+    op, s, m = S["op"], S["s"], S["m"]
+    from oracle.solve import direct, equilibration, BlockJacobi
+    from oracle.post import remove_v_mean
+    b = s.rhs(cube_current(m, 0))
+    xs = remove_v_mean(s, direct(s, b))
+    rng = np.random.default_rng(23)
+    xk = xs + 0.05 * np.abs(xs).max() * (rng.normal(size=s.ndof) + 1j * rng.normal(size=s.ndof))
+    r = b - s.matvec(xk)
+    e = xs - xk
+    X, cs, w = op.gnn_pair(torch.from_numpy(b).cuda(), torch.from_numpy(xk).cuda(), torch.from_numpy(xs).cuda())
+    sc = equilibration(s)
+    bj = BlockJacobi.build(s, m.xyz, 64, scale=sc)
+    rt, et = sc * r, e / sc
+    zt = bj.apply(rt)
+    dsig = G.dof_sigma(s.topo, np.asarray(m.tet), m.region, S["sig"])
+    stat = G.static_features(S["sub"], s.topo.ne, dsig, S["omega"])
+    assert np.abs(op.gnn_static_features() - stat).max() <= 1e-6
+    Xo = G.features(S["sub"], rt, zt, stat)
+    cso, wo = G.targets(S["sub"], zt, et)
+    assert np.abs(X.cpu().numpy() - Xo).max() <= 1e-6 * max(1.0, np.abs(Xo).max())
+    cg = cs.cpu().numpy()
+    assert np.abs((cg[:, 0] + 1j * cg[:, 1]) - cso).max() <= 1e-6 * max(1.0, np.abs(cso).max())
+    assert np.abs(w.cpu().numpy() - wo).max() <= 1e-6 * max(1e-3, wo.max())
+
+
+def test_learned_solve_converges_and_falls_back():
+    """A network that annihilates every direction (c_p = -1) makes its cycles
+    useless: the plain residual judges them and the solve falls back and
+    converges; a mild network keeps the learned cycles and converges too."""
+    S = c1()
+    op, s, m = S["op"], S["s"], S["m"]
+    b = torch.from_numpy(s.rhs(cube_current(m, 0))).cuda()
+    x0, r0 = op.solve(b, tol=1e-10, restart=30, max_iter=5000)
+    th = np.zeros(G.N_PARAMS, np.float32)
+    th[G.N_PARAMS - G.F_OUT] = -1.0                       # b3[0] = -1, all else 0: c_p = -1
+    xb, rb = op.solve(b, tol=1e-10, restart=30, max_iter=5000, gnn_theta=_dev(th))
+    assert rb.converged and rb.fell_back and rb.learned_cycles >= 1
+    assert (torch.linalg.norm(xb - x0) / torch.linalg.norm(x0)).item() <= 1e-7
+    th2 = G.init_params(7).astype(np.float32) * 0.01
+    xl, rl = op.solve(b, tol=1e-10, restart=30, max_iter=5000, gnn_theta=_dev(th2))
+    assert rl.converged and rl.relres <= 1e-10
+    assert (torch.linalg.norm(xl - x0) / torch.linalg.norm(x0)).item() <= 1e-7
+    print(f"plain {r0.iters} iters; annihilating net {rb.iters} (fell back {rb.fell_back}); "
+          f"mild net {rl.iters} iters, {rl.learned_cycles} learned cycles, fell back {rl.fell_back}")
