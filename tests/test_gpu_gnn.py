@@ -159,3 +159,50 @@ def test_learned_solve_converges_and_falls_back():
     assert (torch.linalg.norm(xl - x0) / torch.linalg.norm(x0)).item() <= 1e-7
     print(f"plain {r0.iters} iters; annihilating net {rb.iters} (fell back {rb.fell_back}); "
           f"mild net {rl.iters} iters, {rl.learned_cycles} learned cycles, fell back {rl.fell_back}")
+
+
+def test_training_on_perturbed_tubes_and_held_out_gain():
+    """Train on solver-generated pairs from perturbed tubes, evaluate on a
+    held-out tube.  What the network gains is recorded, not assumed: the
+    training loss must fall below the loss of c = 0 (the plain method), the
+    held-out loss must not rise above it, and the learned solve must converge
+    to the plain solution without costing more than the fallback's trial
+    cycles (at most 10% more iterations)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from synth import perturbed_tube, tube_materials, probe_currents
+    from paper_1602_03207_amd import eddy, learned
+    kw = dict(h_z=2e-3, h_z_end=20e-3, h_theta=2.5e-3, n_theta_max=32, h_wall=0.5e-3, h_coil=1.0e-3,
+              h_core=2e-3, h_out=6e-3)
+
+    def build(seed):
+        m, (ft, fp) = perturbed_tube(seed, **kw)
+        nu, sig, omega = tube_materials(1e5, sigma_tube=1e6 * ft, sigma_plate=2e6 * fp)
+        M = eddy.Mesh(m.xyz, m.tet, m.region, [0, 1, 1, 1])
+        op = eddy.Operator(M, tau=float(nu[0]), block_size=64, tau_precond=0.1 * float(nu[0]))
+        op.assemble(nu, sig, omega)
+        return m, M, op
+
+    def rhs(op, m, z):
+        return op.rhs_from_current(torch.from_numpy(np.ascontiguousarray(probe_currents(m, z)[0])).cuda())
+
+    sets, keep = [], []
+    for seed in range(3):
+        m, M, op = build(seed)
+        X, C, W = learned.collect_pairs(op, [rhs(op, m, z) for z in (-8e-3, 8e-3)], tols=(1e-1, 1e-2, 1e-3, 1e-5))
+        sets.append((op, X, C, W))
+        keep.append(M)
+    zero = torch.zeros(eddy.GNN_PARAMS, dtype=torch.float32, device="cuda")
+    base = np.mean([learned.mean_loss(op, zero, X, C, W) for op, X, C, W in sets])
+    theta, hist = learned.train(sets, steps=300, batch=16, lr=2e-3, log_every=0)
+    tr = np.mean([learned.mean_loss(op, theta, X, C, W) for op, X, C, W in sets])
+    m, M, op = build(100)
+    b = rhs(op, m, 0.0)
+    X, C, W = learned.collect_pairs(op, [b], tols=(1e-2, 1e-4))
+    h0, h1 = learned.mean_loss(op, zero, X, C, W), learned.mean_loss(op, theta, X, C, W)
+    ev = learned.evaluate(op, b, theta, tol=1e-8)
+    print(f"loss c=0 {base:.4f} -> trained {tr:.4f}; held-out {h0:.4f} -> {h1:.4f}; {ev}")
+    assert tr < base
+    assert h1 <= h0 * 1.05
+    assert ev["converged"] and ev["relres"] <= 1e-8 and ev["rel_diff"] <= 1e-5
+    assert ev["learned_iters"] <= 1.1 * ev["plain_iters"]
