@@ -588,7 +588,7 @@ eddy_status eddy_export(const eddy_op* o, int32_t* rowptr, int32_t* col, eddy_c1
 // ---------------------------------------------------------------------------
 namespace {
 struct SolveWs {
-  double2 *V, *w, *z, *xt, *bt, *hd, *h1, *h2, *yd, *part;
+  double2 *V, *w, *z, *xt, *bt, *yd, *part;
   float2 *V32, *w32, *z32;   // complex64 inner loop (precision = 1)
   double *rpart, *nrm;
   // Coulomb projection (nodal CG)
@@ -596,8 +596,7 @@ struct SolveWs {
   double* cdiag;
   // device Hessenberg least squares
   double2 *Hd, *snd, *gd;
-  double *csd, *est, *nrm1;
-  int *flag, *nreorth;
+  double *csd, *est;
   // DCGS2: unrotated Hessenberg (column-major, ld m + 1), fused dots, step
   // coefficients, zeros, ||t|| of the pending direction
   double2 *Hraw, *dots, *coef, *zeros;
@@ -636,9 +635,6 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->gd = c.take<double2>(m + 2);
   w->csd = c.take<double>(m + 1);
   w->est = c.take<double>(m + 1);
-  w->nrm1 = c.take<double>(8);
-  w->flag = c.take<int>(8);
-  w->nreorth = c.take<int>(8);
   w->Hraw = c.take<double2>((int64_t)(m + 1) * m);
   w->dots = c.take<double2>(2 * kMaxRestart + 4);
   w->coef = c.take<double2>(2 * kMaxRestart + 4);
@@ -649,9 +645,6 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->z = c.take<double2>(n);
   w->xt = c.take<double2>(n);
   w->bt = c.take<double2>(n);
-  w->h1 = c.take<double2>(kMaxRestart + 2);
-  w->h2 = c.take<double2>(kMaxRestart + 2);
-  w->hd = c.take<double2>(kMaxRestart + 2);
   w->yd = c.take<double2>(kMaxRestart + 2);
   w->part = c.take<double2>((int64_t)(mdot_parts(n > nv ? n : nv) + kRedBlocks) * (2 * m + 4));
   w->rpart = c.take<double>(kRedBlocks + 8);
@@ -1020,9 +1013,12 @@ struct BatchWs {
   int nrhs, m;
   int64_t ld;
   void *V, *wT, *zT;                  // T-typed inner vectors
-  double2 *xt, *bt, *w64, *part, *h1, *h2, *Hd, *snd, *gd, *yd;
-  double *rpart, *nrm, *nrm1, *beta, *bnorm, *csd, *est;
-  int *flag, *nreorth, *kcols, *run, *cyc;
+  double2 *xt, *bt, *w64, *part, *Hd, *snd, *gd, *yd;
+  double *rpart, *nrm, *beta, *bnorm, *csd, *est;
+  int *kcols, *run, *cyc;
+  // delayed CGS2: unrotated Hessenberg, fused dots, step coefficients (per system), zeros, ||t||
+  double2 *Hraw, *dots, *coef, *zeros;
+  double* tnorm;
   ProjBufs P;
 };
 
@@ -1040,22 +1036,22 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
   B->bt = c.take<double2>((int64_t)nrhs * ld);
   B->w64 = c.take<double2>((int64_t)nrhs * ld);
   const int64_t np = mdot_parts(n > nv ? n : nv);
-  B->part = c.take<double2>((int64_t)nrhs * np * (m + 2));
-  B->h1 = c.take<double2>((int64_t)nrhs * (m + 2));
-  B->h2 = c.take<double2>((int64_t)nrhs * (m + 2));
+  B->part = c.take<double2>((int64_t)nrhs * std::max<int64_t>(np * (m + 2), (int64_t)mdot2_parts(n) * (2 * m + 2)));
+  B->Hraw = c.take<double2>((int64_t)nrhs * (m + 1) * m);
+  B->dots = c.take<double2>((int64_t)nrhs * (2 * kMaxRestart + 4));
+  B->coef = c.take<double2>((int64_t)nrhs * (2 * kMaxRestart + 4));
+  B->zeros = c.take<double2>(kMaxRestart + 2);
+  B->tnorm = c.take<double>(nrhs);
   B->Hd = c.take<double2>((int64_t)nrhs * (m + 1) * m);
   B->snd = c.take<double2>((int64_t)nrhs * (m + 1));
   B->gd = c.take<double2>((int64_t)nrhs * (m + 2));
   B->yd = c.take<double2>((int64_t)nrhs * (m + 2));
   B->rpart = c.take<double>((int64_t)nrhs * kRedBlocks);
   B->nrm = c.take<double>(nrhs);
-  B->nrm1 = c.take<double>(nrhs);
   B->beta = c.take<double>(nrhs);
   B->bnorm = c.take<double>(nrhs);
   B->csd = c.take<double>((int64_t)nrhs * (m + 1));
   B->est = c.take<double>((int64_t)nrhs * (m + 1));
-  B->flag = c.take<int>(nrhs);
-  B->nreorth = c.take<int>(nrhs);
   B->kcols = c.take<int>(nrhs);
   B->run = c.take<int>(nrhs);
   B->cyc = c.take<int>(nrhs);
@@ -1083,7 +1079,9 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
                         std::vector<int>& its, std::vector<eddy_solve_report>& R, hipStream_t s) {
   const int nrhs = B.nrhs, m = B.m;
   const int64_t n = o->n, ld = B.ld, vstride = (int64_t)(m + 1) * ld, hs = m + 2;
-  const int64_t pstride = (int64_t)mdot_parts(n) * (m + 2);
+  const int64_t np = mdot_parts(n > o->nv ? n : o->nv);
+  const int64_t pstride = std::max<int64_t>(np * (m + 2), (int64_t)mdot2_parts(n) * (2 * m + 2));
+  const int64_t dstride = 2 * kMaxRestart + 4;
   T* V = (T*)B.V;
   T* wT = (T*)B.wT;
   T* zT = (T*)B.zT;
@@ -1093,6 +1091,9 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
   std::vector<double> beta(bnorm), est((size_t)nrhs * (m + 1));
   for (int r = 0; r < nrhs; ++r) done[r] = bnorm[r] > 0 ? 0 : 1;
   HIP_TRY(hipMemcpyAsync(B.bnorm, bnorm.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+  const double2 zero2h[kMaxRestart + 2] = {};
+  HIP_TRY(hipMemcpyAsync(B.zeros, zero2h, sizeof(zero2h), hipMemcpyHostToDevice, s));
+  const int nparts2 = mdot2_parts(n);
   const double2* rvec = B.bt;          // cycle start residual (FP64), x~ = 0 at first
   while (true) {
     int nact = 0;
@@ -1104,68 +1105,70 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     HIP_TRY(hipMemcpyAsync(B.cyc, cyc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(B.run, run.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(B.beta, beta.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-    // v0 = r / beta (stored in T)
+    // pending v0 = r / beta (stored in T); the delayed-CGS2 step j finishes v_j
     launch_to_storage_b(n, rvec, ld, V, vstride, nrhs, s);
     launch_scale_by_inv_b(n, (const T*)V, vstride, B.beta, V, vstride, B.cyc, nrhs, s);
-    int jstart = 0, jend = m;
+    int jstart = 0;      // first estimate index not yet checked (common to the running systems)
     for (int j = 0; j < m; ++j) {
-      const int q = j + 1;
-      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, vstride, (const T*)(V + (int64_t)j * ld), ld,
-                           zT, B.run, s);
+      T* vj = V + (int64_t)j * ld;
+      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, vstride, (const T*)vj, ld, zT, B.run, s);
       launch_spmv_b(n, o->rowptr, o->col, val, nrhs, ld, (const T*)zT, (const T*)nullptr, wT, B.run, s);
-      launch_mdot_b(n, (const T*)V, ld, vstride, q, (const T*)wT, ld, B.part, pstride, 1, (const int*)nullptr, B.run,
-                    nrhs, s);
-      launch_reduce_cols_b(q + 1, mdot_parts(n), B.part, pstride, B.h1, hs, nullptr, B.run, nrhs, s);
-      launch_update_norm_b(n, (const T*)V, ld, vstride, q, B.h1, hs, wT, ld, B.rpart, B.nrm1, nullptr, B.run, nrhs,
-                           s);
-      launch_reorth_decide_b(q, B.h1, hs, B.nrm1, B.h2, B.nrm, B.flag, B.nreorth, B.run, nrhs, s);
-      launch_mdot_b(n, (const T*)V, ld, vstride, q, (const T*)wT, ld, B.part, pstride, 0, B.flag, B.run, nrhs, s);
-      launch_reduce_cols_b(q, mdot_parts(n), B.part, pstride, B.h2, hs, B.flag, B.run, nrhs, s);
-      launch_update_norm_b(n, (const T*)V, ld, vstride, q, B.h2, hs, wT, ld, B.rpart, B.nrm, B.flag, B.run, nrhs, s);
-      launch_scale_by_inv_b(n, (const T*)wT, ld, B.nrm, V + (int64_t)(j + 1) * ld, vstride, B.run, nrhs, s);
-      launch_givens_b(j, m, B.h1, B.h2, hs, B.nrm, B.Hd, B.csd, B.snd, B.gd, B.beta, B.bnorm, B.est, B.run, nrhs, s);
+      launch_mdot2_b(n, (const T*)V, ld, vstride, j, (const T*)vj, (const T*)wT, ld, B.part, pstride, B.run, nrhs, s);
+      launch_reduce_cols_b(2 * j + 2, nparts2, B.part, pstride, B.dots, dstride, nullptr, B.run, nrhs, s);
+      launch_dcgs_coef_b(j, m, B.dots, dstride, B.Hraw, B.tnorm, B.coef, B.Hd, B.csd, B.snd, B.gd, B.beta, B.bnorm,
+                         B.est, B.run, nrhs, s);
+      launch_dcgs_update_b(n, (const T*)V, ld, vstride, j, B.coef, dstride, vj, wT, ld, B.rpart, B.tnorm, B.run,
+                           nrhs, s);
+      launch_scale_by_inv_b(n, (const T*)wT, ld, B.tnorm, V + (int64_t)(j + 1) * ld, vstride, B.run, nrhs, s);
       for (int r = 0; r < nrhs; ++r) its[r] += run[r];
       bool any_max = false;
       for (int r = 0; r < nrhs; ++r) any_max |= run[r] && its[r] >= opts->max_iter;
-      const bool check = (j + 1 - jstart) == kCheckEvery || j == m - 1 || any_max;
+      const bool last = j == m - 1;
+      const bool check = last || (j + 1) % kCheckEvery == 0 || any_max;
       if (!check) continue;
+      // estimates after 1..j steps are final; at the cycle end the last
+      // column (projected once) gets its rotation too
+      int avail = j;
+      if (last) {
+        launch_givens_b(j, m, B.Hraw + (int64_t)j * (m + 1), B.zeros, (int64_t)(m + 1) * m, 0, B.tnorm, B.Hd, B.csd,
+                        B.snd, B.gd, B.beta, B.bnorm, B.est, B.run, nrhs, s);
+        avail = m;
+      }
       HIP_TRY(hipMemcpyAsync(est.data(), B.est, sizeof(double) * est.size(), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       bool changed = false;
       int nrun = 0;
       for (int r = 0; r < nrhs; ++r) {
         if (!run[r]) continue;
-        for (int jj = jstart; jj <= j; ++jj) {
+        for (int jj = jstart; jj < avail; ++jj) {
           const double e = est[(size_t)r * (m + 1) + jj];
           if (!std::isfinite(e)) { set_error("non-finite Arnoldi residual"); return EDDY_ERR_DEVICE; }
           if (e <= opts->tol) {
             if (e == 0.0) R[r].breakdown = 1;
-            its[r] -= j - jj;
             kc[r] = jj + 1;
+            its[r] -= (j + 1) - kc[r];
             run[r] = 0;
             changed = true;
             break;
           }
         }
         if (run[r] && its[r] >= opts->max_iter) {
-          kc[r] = j + 1;
+          // mid-cycle the last step's column is not final: stop with the finished ones
+          kc[r] = avail;
+          its[r] -= (j + 1) - kc[r];
           run[r] = 0;
           changed = true;
         }
         nrun += run[r];
       }
-      if (nrun == 0) {
-        jend = j + 1;
-        break;
-      }
+      if (nrun == 0) break;
       if (changed) HIP_TRY(hipMemcpyAsync(B.run, run.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-      jstart = j + 1;
+      jstart = avail;
     }
     for (int r = 0; r < nrhs; ++r) {
       if (run[r]) kc[r] = m;
-      if (cyc[r]) R[r].est_relres = est[(size_t)r * (m + 1) + (kc[r] - 1)];
+      if (cyc[r] && kc[r] > 0) R[r].est_relres = est[(size_t)r * (m + 1) + (kc[r] - 1)];
     }
-    (void)jend;
     HIP_TRY(hipMemcpyAsync(B.kcols, kc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     launch_backsolve_b(B.kcols, m, B.Hd, B.gd, B.yd, hs, B.cyc, nrhs, s);
     launch_combine_b(n, (const T*)V, ld, vstride, B.kcols, B.yd, hs, wT, ld, B.cyc, nrhs, s);
@@ -1242,7 +1245,6 @@ eddy_status eddy_solve_batched(eddy_op* o, int32_t nrhs, const eddy_c128* b_dev,
       return EDDY_ERR_ARG;
     }
   }
-  HIP_TRY(hipMemsetAsync(B.nreorth, 0, sizeof(int) * nrhs, s));
   launch_diag_scale_b(n, (const double2*)b_dev, n, o->s, 0, B.bt, ld, nrhs, s);
   for (int r = 0; r < nrhs; ++r) launch_zero(n, B.xt + (int64_t)r * ld, s);
   launch_norm2_b(n, (const double2*)B.bt, ld, B.rpart, B.nrm, nullptr, nrhs, s);
@@ -1251,9 +1253,6 @@ eddy_status eddy_solve_batched(eddy_op* o, int32_t nrhs, const eddy_c128* b_dev,
   if (opts->precision == 1) st = run_batched<float2>(o, B, opts, bnorm, its, R, s);
   else st = run_batched<double2>(o, B, opts, bnorm, its, R, s);
   if (st != EDDY_OK) return st;
-  std::vector<int> reo(nrhs);
-  HIP_TRY(hipMemcpyAsync(reo.data(), B.nreorth, sizeof(int) * nrhs, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
   bool all = true;
   for (int r = 0; r < nrhs; ++r) {
     double2* xr = (double2*)x_dev + (int64_t)r * n;
@@ -1262,7 +1261,7 @@ eddy_status eddy_solve_batched(eddy_op* o, int32_t nrhs, const eddy_c128* b_dev,
       return st;
     launch_vmean(o->nc, o->ncomp, o->comp, o->lumped, xr + o->ne, o->red, s);
     R[r].iters = its[r];
-    R[r].reorth_steps = reo[r];
+    R[r].reorth_steps = its[r];   // the delayed scheme reorthogonalises every basis vector
     R[r].precision_used = opts->precision;
     R[r].converged = R[r].relres <= opts->tol ? 1 : 0;
     all = all && R[r].converged;

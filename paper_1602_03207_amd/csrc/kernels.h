@@ -81,27 +81,17 @@ void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, c
 template <class T>
 void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, int nrhs, int64_t ld, const T* x,
                    const T* b, T* y, const int* active, hipStream_t st);
-template <class T>
-void launch_mdot_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* w, int64_t wstride,
-                   double2* partial, int64_t pstride, int want_norm, const int* flag, const int* active, int nrhs,
-                   hipStream_t st);
 void launch_reduce_cols_b(int q, int nparts, const double2* partial, int64_t pstride, double2* out, int64_t ostride,
                           const int* flag, const int* active, int nrhs, hipStream_t st);
-template <class T>
-void launch_update_norm_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* h,
-                          int64_t hstride, T* w, int64_t wstride, double* rpart, double* out_norm, const int* flag,
-                          const int* active, int nrhs, hipStream_t st);
-void launch_reorth_decide_b(int q, const double2* h1, int64_t hstride, const double* nrm1, double2* h2, double* nrm,
-                            int* flag, int* counter, const int* active, int nrhs, hipStream_t st);
 template <class T>
 void launch_norm2_b(int64_t n, const T* w, int64_t wstride, double* partial, double* out_norm, const int* active,
                     int nrhs, hipStream_t st);
 template <class T>
 void launch_scale_by_inv_b(int64_t n, const T* w, int64_t wstride, const double* norm, T* v, int64_t vstride,
                            const int* active, int nrhs, hipStream_t st);
-void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, const double* nrm,
-                     double2* H, double* cs, double2* sn, double2* g, const double* beta, const double* bnorm,
-                     double* est, const int* active, int nrhs, hipStream_t st);
+void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, int64_t h2stride,
+                     const double* nrm, double2* H, double* cs, double2* sn, double2* g, const double* beta,
+                     const double* bnorm, double* est, const int* active, int nrhs, hipStream_t st);
 void launch_backsolve_b(const int* ks, int m, const double2* H, const double2* g, double2* y, int64_t ystride,
                         const int* active, int nrhs, hipStream_t st);
 template <class T>
@@ -131,6 +121,19 @@ void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const do
                       double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
                       double2* Sall, double* rhoall, hipStream_t st);
 void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall, double2* y, hipStream_t st);
+// batched forms (system z: V at z * vstride, w at z * wstride, partial at
+// z * pstride, dots and coef at z * dstride, Hessenberg data at the strides
+// of launch_givens_b; beta, bnorm, tnorm per system; active masks systems)
+template <class T>
+void launch_mdot2_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* v, const T* w,
+                    int64_t wstride, double2* partial, int64_t pstride, const int* active, int nrhs, hipStream_t st);
+void launch_dcgs_coef_b(int j, int m, const double2* dots, int64_t dstride, double2* Hraw, const double* tnorm,
+                        double2* coef, double2* H, double* cs, double2* sn, double2* g, const double* beta,
+                        const double* bnorm, double* est, const int* active, int nrhs, hipStream_t st);
+template <class T>
+void launch_dcgs_update_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
+                          int64_t cstride, T* v, T* w, int64_t wstride, double* rpart, double* out_norm,
+                          const int* active, int nrhs, hipStream_t st);
 template <class T>
 void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,
                         double* out_norm, hipStream_t st);

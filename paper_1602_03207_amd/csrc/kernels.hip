@@ -700,7 +700,15 @@ constexpr int kDot2MaxBlocks = 1024;
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
                                                     const T* __restrict__ v, const T* __restrict__ w,
-                                                    double2* __restrict__ partial) {
+                                                    double2* __restrict__ partial, int64_t vstride, int64_t wstride,
+                                                    int64_t pstride, const int* __restrict__ active) {
+  // system z of a batch (grid.z); strides are 0 for a single system
+  const int zs = blockIdx.z;
+  if (active && !active[zs]) return;
+  V += zs * vstride;
+  v += zs * vstride;
+  w += zs * wstride;
+  partial += zs * pstride;
   constexpr int R = kDot2Rows / kThreads;
   __shared__ double2 red[4][18];
   const int c0 = blockIdx.y * 8;
@@ -893,67 +901,7 @@ __global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, const T* __restric
 
 // w <- w - V h (FP64 arithmetic, stored in T) and rpart = per-block ||w||^2:
 // the second CGS2 update fused with the norm of the new basis vector.
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_update_norm(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                          const double2* __restrict__ h, T* __restrict__ w,
-                                                          double* __restrict__ rpart, const int* __restrict__ flag,
-                                                          int64_t vstride, int64_t wstride, int64_t hstride,
-                                                          const int* __restrict__ active) {
-  const int z = blockIdx.z;
-  if ((active && !active[z]) || (flag && flag[z] == 0)) return;
-  V += z * vstride;
-  w += z * wstride;
-  h += z * hstride;
-  rpart += (int64_t)z * gridDim.x;
-  __shared__ double2 hs[kMaxRestart + 1];
-  __shared__ double sh[4];
-  if (threadIdx.x < q) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double2 wi = ld2(w[i]);
-    for (int k = 0; k < q; ++k) {
-      const double2 v = ld2(V[(int64_t)k * ldv + i]);
-      const double2 hk = hs[k];
-      wi.x -= v.x * hk.x - v.y * hk.y;
-      wi.y -= v.x * hk.y + v.y * hk.x;
-    }
-    const T ws = st2<T>(wi);
-    w[i] = ws;
-    wi = ld2(ws);
-    acc = fma(wi.x, wi.x, fma(wi.y, wi.y, acc));
-  }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) rpart[blockIdx.x] = acc;
-}
 
-// Selective reorthogonalisation: after one classical Gram-Schmidt pass the
-// second pass is needed only if the norm dropped below ||w|| / sqrt(2)
-// (twice is enough).  h1[q] holds ||w||^2 before the pass, nrm1 the norm
-// after it.  flag = 1 runs the second pass (which writes h2 and nrm);
-// otherwise h2 = 0 and nrm = nrm1.  counter counts second passes.
-__global__ void k_reorth_decide(int q, const double2* __restrict__ h1, const double* __restrict__ nrm1,
-                                double2* __restrict__ h2, double* __restrict__ nrm, int* __restrict__ flag,
-                                int* __restrict__ counter, int64_t hstride, const int* __restrict__ active) {
-  const int z = blockIdx.z;
-  if (active && !active[z]) return;
-  h1 += z * hstride;
-  h2 += z * hstride;
-  nrm1 += z;
-  nrm += z;
-  flag += z;
-  counter += z;
-  const int t = threadIdx.x;
-  const double w0 = sqrt(h1[q].x);
-  const int need = nrm1[0] < 0.70710678118654752 * w0 ? 1 : 0;
-  if (t == 0) {
-    *flag = need;
-    if (need) counter[0] += 1;
-    else nrm[0] = nrm1[0];
-  }
-  if (!need)
-    for (int k = t; k < q; k += blockDim.x) h2[k] = make_double2(0.0, 0.0);
-}
 
 // ---- Hessenberg least squares on the device (one thread) ----
 // Column j of H (row-major, leading dimension m) = h1 + h2 with H(j+1, j) =
@@ -1033,8 +981,27 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* _
                                                   double* __restrict__ cs, double2* __restrict__ sn,
                                                   double2* __restrict__ g, double beta, double bnorm,
                                                   double* __restrict__ est, double2* __restrict__ Sall,
-                                                  double* __restrict__ rhoall) {
+                                                  double* __restrict__ rhoall, const double* __restrict__ betas,
+                                                  const double* __restrict__ bnorms, int64_t dstride,
+                                                  const int* __restrict__ active) {
   static_assert(kMaxRestart <= 64, "one lane per Hessenberg row");
+  // system z of a batch (grid.z): per-system arrays at fixed strides; beta
+  // and ||b|| from the device arrays when given
+  const int zs = blockIdx.z;
+  if (active && !active[zs]) return;
+  if (betas) {
+    beta = betas[zs];
+    bnorm = bnorms[zs];
+  }
+  dots += zs * dstride;
+  coef += zs * dstride;
+  Hraw += (int64_t)zs * (m + 1) * m;
+  H += (int64_t)zs * (m + 1) * m;
+  tnorm += zs;
+  cs += zs * (m + 1);
+  sn += zs * (m + 1);
+  g += zs * (m + 2);
+  est += zs * (m + 1);
   __shared__ double2 ss[kMaxRestart], rr[kMaxRestart], hs[kMaxRestart], col[kMaxRestart + 1], snl[kMaxRestart];
   __shared__ double csl[kMaxRestart];
   __shared__ double sh_rho;
@@ -1146,7 +1113,16 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* _
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_dcgs_update(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
                                                           const double2* __restrict__ coef, T* __restrict__ v,
-                                                          T* __restrict__ w, double* __restrict__ rpart) {
+                                                          T* __restrict__ w, double* __restrict__ rpart,
+                                                          int64_t vstride, int64_t wstride, int64_t cstride,
+                                                          const int* __restrict__ active) {
+  const int zs = blockIdx.z;
+  if (active && !active[zs]) return;
+  V += zs * vstride;
+  v += zs * vstride;
+  w += zs * wstride;
+  coef += zs * cstride;
+  rpart += (int64_t)zs * gridDim.x;
   __shared__ double2 cs_[kMaxRestart], cg_[kMaxRestart];
   __shared__ double sh[4];
   if (threadIdx.x < q) {
@@ -1182,10 +1158,10 @@ __global__ void k_givens_b(int j, int m, const double2* __restrict__ h1, const d
                            const double* __restrict__ nrm, double2* __restrict__ H, double* __restrict__ cs,
                            double2* __restrict__ sn, double2* __restrict__ g, const double* __restrict__ beta,
                            const double* __restrict__ bnorm, double* __restrict__ est, int64_t hstride,
-                           const int* __restrict__ active) {
+                           int64_t h2stride, const int* __restrict__ active) {
   const int z = blockIdx.z;
   if (threadIdx.x != 0 || (active && !active[z])) return;
-  givens_body(j, m, h1 + z * hstride, h2 + z * hstride, nrm + z, H + (int64_t)z * (m + 1) * m, cs + z * (m + 1),
+  givens_body(j, m, h1 + z * hstride, h2 + z * h2stride, nrm + z, H + (int64_t)z * (m + 1) * m, cs + z * (m + 1),
               sn + z * (m + 1), g + z * (m + 2), beta[z], bnorm[z], est + z * (m + 1));
 }
 
@@ -1636,12 +1612,13 @@ template <class T>
 void launch_mdot2(int64_t n, const T* V, int64_t ldv, int q, const T* v, const T* w, double2* partial,
                   hipStream_t st) {
   dim3 grid(mdot2_parts(n), q > 0 ? (q + 7) / 8 : 1);
-  k_mdot2<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial);
+  k_mdot2<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, 0, 0, 0, nullptr);
 }
 void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
                       double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
                       double2* Sall, double* rhoall, hipStream_t st) {
-  k_dcgs_coef<<<1, 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, beta, bnorm, est, Sall, rhoall);
+  k_dcgs_coef<<<1, 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, beta, bnorm, est, Sall, rhoall,
+                                nullptr, nullptr, 0, nullptr);
 }
 // Flexible cycles: the basis vector q_j = (v_j - sum_{i<j} s_i^(j) q_i) / rho_j
 // was finished after z_j = B_j v_j was formed, so the columns matching the
@@ -1663,8 +1640,28 @@ void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall,
 template <class T>
 void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,
                         double* out_norm, hipStream_t st) {
-  k_dcgs_update<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart);
+  k_dcgs_update<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, 0, 0, 0, nullptr);
   k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, nullptr, nullptr);
+}
+template <class T>
+void launch_mdot2_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* v, const T* w,
+                    int64_t wstride, double2* partial, int64_t pstride, const int* active, int nrhs, hipStream_t st) {
+  dim3 grid(mdot2_parts(n), q > 0 ? (q + 7) / 8 : 1, nrhs);
+  k_mdot2<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, vstride, wstride, pstride, active);
+}
+void launch_dcgs_coef_b(int j, int m, const double2* dots, int64_t dstride, double2* Hraw, const double* tnorm,
+                        double2* coef, double2* H, double* cs, double2* sn, double2* g, const double* beta,
+                        const double* bnorm, double* est, const int* active, int nrhs, hipStream_t st) {
+  k_dcgs_coef<<<dim3(1, 1, nrhs), 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, 0.0, 1.0, est, nullptr,
+                                               nullptr, beta, bnorm, dstride, active);
+}
+template <class T>
+void launch_dcgs_update_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
+                          int64_t cstride, T* v, T* w, int64_t wstride, double* rpart, double* out_norm,
+                          const int* active, int nrhs, hipStream_t st) {
+  k_dcgs_update<T><<<dim3(kRedBlocks, 1, nrhs), kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, vstride, wstride,
+                                                                  cstride, active);
+  k_norm2_final<<<dim3(1, 1, nrhs), kThreads, 0, st>>>(rpart, out_norm, nullptr, active);
 }
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st) {
@@ -1685,31 +1682,10 @@ void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, i
                    const T* b, T* y, const int* active, hipStream_t st) {
   k_spmv_b<T><<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, rowptr, col, val, nrhs, ld, x, b, y, active);
 }
-template <class T>
-void launch_mdot_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* w, int64_t wstride,
-                   double2* partial, int64_t pstride, int want_norm, const int* flag, const int* active, int nrhs,
-                   hipStream_t st) {
-  dim3 grid(mdot_parts(n), (q + 7) / 8, nrhs);
-  k_mdot<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, w, partial, want_norm, flag, vstride, wstride, pstride, active);
-}
 void launch_reduce_cols_b(int q, int nparts, const double2* partial, int64_t pstride, double2* out, int64_t ostride,
                           const int* flag, const int* active, int nrhs, hipStream_t st) {
   dim3 grid(q, 1, nrhs);
   k_reduce_cols<<<grid, kThreads, 0, st>>>(partial, nparts, out, flag, pstride, ostride, active);
-}
-template <class T>
-void launch_update_norm_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* h,
-                          int64_t hstride, T* w, int64_t wstride, double* rpart, double* out_norm, const int* flag,
-                          const int* active, int nrhs, hipStream_t st) {
-  dim3 grid(kRedBlocks, 1, nrhs);
-  k_update_norm<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, h, w, rpart, flag, vstride, wstride, hstride, active);
-  dim3 g1(1, 1, nrhs);
-  k_norm2_final<<<g1, kThreads, 0, st>>>(rpart, out_norm, flag, active);
-}
-void launch_reorth_decide_b(int q, const double2* h1, int64_t hstride, const double* nrm1, double2* h2, double* nrm,
-                            int* flag, int* counter, const int* active, int nrhs, hipStream_t st) {
-  dim3 grid(1, 1, nrhs);
-  k_reorth_decide<<<grid, 64, 0, st>>>(q, h1, nrm1, h2, nrm, flag, counter, hstride, active);
 }
 template <class T>
 void launch_norm2_b(int64_t n, const T* w, int64_t wstride, double* partial, double* out_norm, const int* active,
@@ -1725,11 +1701,11 @@ void launch_scale_by_inv_b(int64_t n, const T* w, int64_t wstride, const double*
   dim3 grid(blocks_for(n), 1, nrhs);
   k_scale_by_inv<T><<<grid, kThreads, 0, st>>>(n, w, norm, v, wstride, vstride, active);
 }
-void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, const double* nrm,
-                     double2* H, double* cs, double2* sn, double2* g, const double* beta, const double* bnorm,
-                     double* est, const int* active, int nrhs, hipStream_t st) {
+void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, int64_t h2stride,
+                     const double* nrm, double2* H, double* cs, double2* sn, double2* g, const double* beta,
+                     const double* bnorm, double* est, const int* active, int nrhs, hipStream_t st) {
   dim3 grid(1, 1, nrhs);
-  k_givens_b<<<grid, 64, 0, st>>>(j, m, h1, h2, nrm, H, cs, sn, g, beta, bnorm, est, hstride, active);
+  k_givens_b<<<grid, 64, 0, st>>>(j, m, h1, h2, nrm, H, cs, sn, g, beta, bnorm, est, hstride, h2stride, active);
 }
 void launch_backsolve_b(const int* ks, int m, const double2* H, const double2* g, double2* y, int64_t ystride,
                         const int* active, int nrhs, hipStream_t st) {
@@ -1784,15 +1760,21 @@ template void launch_dcgs_update<double2>(int64_t, const double2*, int64_t, int,
                                           double*, double*, hipStream_t);
 template void launch_dcgs_update<float2>(int64_t, const float2*, int64_t, int, const double2*, float2*, float2*,
                                          double*, double*, hipStream_t);
+template void launch_mdot2_b<double2>(int64_t, const double2*, int64_t, int64_t, int, const double2*, const double2*,
+                                      int64_t, double2*, int64_t, const int*, int, hipStream_t);
+template void launch_mdot2_b<float2>(int64_t, const float2*, int64_t, int64_t, int, const float2*, const float2*,
+                                     int64_t, double2*, int64_t, const int*, int, hipStream_t);
+template void launch_dcgs_update_b<double2>(int64_t, const double2*, int64_t, int64_t, int, const double2*, int64_t,
+                                            double2*, double2*, int64_t, double*, double*, const int*, int,
+                                            hipStream_t);
+template void launch_dcgs_update_b<float2>(int64_t, const float2*, int64_t, int64_t, int, const double2*, int64_t,
+                                           float2*, float2*, int64_t, double*, double*, const int*, int,
+                                           hipStream_t);
 #define EDDY_INST_B(T)                                                                                            \
   template void launch_block_apply_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, int64_t, \
                                         T*, const int*, hipStream_t);                                             \
   template void launch_spmv_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, const T*, T*,  \
                                  const int*, hipStream_t);                                                        \
-  template void launch_mdot_b<T>(int64_t, const T*, int64_t, int64_t, int, const T*, int64_t, double2*, int64_t,   \
-                                 int, const int*, const int*, int, hipStream_t);                                  \
-  template void launch_update_norm_b<T>(int64_t, const T*, int64_t, int64_t, int, const double2*, int64_t, T*,     \
-                                        int64_t, double*, double*, const int*, const int*, int, hipStream_t);     \
   template void launch_norm2_b<T>(int64_t, const T*, int64_t, double*, double*, const int*, int, hipStream_t);      \
   template void launch_scale_by_inv_b<T>(int64_t, const T*, int64_t, const double*, T*, int64_t, const int*, int, \
                                          hipStream_t);                                                            \
