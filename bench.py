@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scan", type=int, default=8,
                     help="also time a batched scan of this many probe positions (0 = skip)")
+    ap.add_argument("--learned-tubes", type=int, default=4,
+                    help="perturbed 258k-tet tubes the learned correction trains on (0 = skip)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
                     help="headline method; 'both' also times plain FP64 for comparison")
     return ap.parse_args()
@@ -104,6 +106,54 @@ def block_apply_bytes(M, op, block, vb=16):
     ptr, _ = M.blocks(block)
     sz = np.diff(ptr).astype(np.int64)
     return int(vb * (sz * sz).sum() + 4 * (len(ptr)) + 4 * op.ndof + 2 * vb * op.ndof)
+
+
+def learned_section(args, op, b, head):
+    """Train the learned coarse correction on perturbed tubes (solver-generated
+    pairs, GPU training kernels), then solve the headline right-hand side with
+    it; untimed by the headline, reported beside it."""
+    import numpy as np
+    import torch
+    from synth import perturbed_tube, tube_materials, probe_currents
+    from paper_1602_03207_amd import eddy, learned
+    kw = dict(h_z=1e-3, h_z_end=20e-3, h_theta=2e-3, n_theta_max=48, h_wall=0.4e-3, h_coil=1.0e-3, h_core=2e-3,
+              h_out=6e-3)
+    t0 = time.perf_counter()
+    sets, keep, nt = [], [], 0
+    for seed in range(args.learned_tubes):
+        m, (ft, fp) = perturbed_tube(seed, **kw)
+        nu, sig, omega = tube_materials(1e5, sigma_tube=1e6 * ft, sigma_plate=2e6 * fp)
+        M = eddy.Mesh(m.xyz, m.tet, m.region, [0, 1, 1, 1])
+        o = eddy.Operator(M, tau=float(nu[0]), block_size=args.block, tau_precond=args.tau_precond_factor * nu[0])
+        o.assemble(nu, sig, omega)
+        B = [o.rhs_from_current(torch.from_numpy(np.ascontiguousarray(probe_currents(m, z)[0])).cuda())
+             for z in (-12e-3, 0.0, 12e-3)]
+        X, C, W = learned.collect_pairs(o, B, restart=args.restart, precision=head)
+        sets.append((o, X, C, W))
+        keep.append(M)
+        nt = m.nt
+    zero = torch.zeros(eddy.GNN_PARAMS, dtype=torch.float32, device="cuda")
+    l0 = float(np.mean([learned.mean_loss(o, zero, X, C, W) for o, X, C, W in sets]))
+    theta, _ = learned.train(sets, steps=400, batch=32, lr=2e-3, log_every=0)
+    l1 = float(np.mean([learned.mean_loss(o, theta, X, C, W) for o, X, C, W in sets]))
+    t_train = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    xp, rp = op.solve(b[0], tol=args.tol, restart=args.restart, max_iter=args.max_iter, precision=head)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    xl, rl = op.solve(b[0], tol=args.tol, restart=args.restart, max_iter=args.max_iter, precision=head,
+                      gnn_theta=theta)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t2
+    tp = t2 - t1
+    diff = float((torch.linalg.norm(xl - xp) / torch.linalg.norm(xp)).item())
+    return {"train": {"tubes": args.learned_tubes, "tets_each": nt, "pairs": int(sum(X.shape[0] for _, X, _, _ in sets)),
+                      "loss_c0": round(l0, 5), "loss_trained": round(l1, 5), "seconds": round(t_train, 1)},
+            "solve_s": round(tl, 4), "iters": rl.iters, "learned_cycles": rl.learned_cycles,
+            "fell_back": rl.fell_back, "converged": rl.converged, "relres": rl.relres,
+            "plain_solve_s": round(tp, 4), "plain_iters": rp.iters,
+            "speedup_vs_plain": round(tp / tl, 3), "rel_diff_vs_plain": diff}
 
 
 def cpu_baseline(args, gpu_iters):
@@ -253,6 +303,10 @@ def main():
                 "speedup_vs_single_headline": round(sec_per_solve / (st / args.scan), 3),
                 "Z11": [[z[0, 0].real, z[0, 0].imag] for z in sZ]}
 
+    learned_out = None
+    if args.learned_tubes and args.workload == "tube":
+        learned_out = learned_section(args, op, b, head)
+
     cpu = None
     if not args.no_cpu_baseline and args.workload == "tube":
         it_cpu = runs["fp64"]["rep"].iters if "fp64" in runs else rep.iters
@@ -288,6 +342,7 @@ def main():
                         "Z11": [runs["fp64"]["Z"][0, 0].real, runs["fp64"]["Z"][0, 0].imag],
                         "kernels": runs["fp64"]["kernels"]} if "fp64" in runs and head != "fp64" else None),
         "batched_scan": scan,
+        "learned": learned_out,
         "host_setup_s": round(host_setup, 2),
         "spmv_tuning": op.tuning(),
         "kernels": kernels,
