@@ -70,6 +70,8 @@ struct eddy_op {
   int *d0ptr, *d0list, *lcptr, *lclist, *rptr, *rlist;
   int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
   int *sell_ptr, *sell_row, *sell_col, *sell_src;
+  int *lrowptr, *lcol;          // L = W^T G pattern (Coulomb projection)
+  int64_t nnzl;
   // numeric
   double2 *val, *ebuf, *minv;
   double* gscr;                 // gauge part of the diagonal blocks (assembly scratch)
@@ -90,6 +92,7 @@ struct eddy_op {
   eddy_tuning tune = {};        // SpMV grid caps (autotuned at the first assembly)
   bool tuned = false;
   double *wval, *wtval, *wbuf, *vol4, *rbuf, *d0, *d0tau, *d0taup, *lumped, *s, *nu_reg, *sig_reg;
+  double *lval, *ldiag;         // L values and diagonal
   double2 *tmp1, *tmp2, *tvec, *red;
   double* rred;
   int* status;
@@ -151,6 +154,10 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->sell_src = c.take<int>(nsell);
   o->sval = c.take<double2>(nsell);
   o->sval32 = c.take<float2>(nsell);
+  o->lrowptr = c.take<int>(m->nv + 1);
+  o->lcol = c.take<int>((int64_t)m->lcol.size());
+  o->lval = c.take<double>((int64_t)m->lcol.size());
+  o->ldiag = c.take<double>(m->nv);
   o->val = c.take<double2>(m->nnz());
   o->ebuf = c.take<double2>(21 * m->nt + 34 * m->nct);
   o->minv = c.take<double2>(nb * kMaxBlock * kMaxBlock);
@@ -398,6 +405,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   o->nnz = m->nnz(); o->nnzw = m->nnzw(); o->nb = (int64_t)m->blk_ptr.size() - 1;
   o->nreg = m->nreg; o->ncomp = m->ncomp; o->bsize = p->block_size;
   o->geom_hash = m->geom_hash;
+  o->nnzl = (int64_t)m->lcol.size();
   o->ns = (int64_t)m->sell_ptr.size() - 1;
   o->nsell = (int64_t)m->sell_col.size();
   o->tau = p->tau_gauge; o->delta_v = p->delta_v;
@@ -422,7 +430,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   UP(o->rptr, m->rptr); UP(o->rlist, m->rlist); UP(o->blk_ptr, m->blk_ptr); UP(o->blk_dofs, m->blk_dofs);
   UP(o->blk_of, blk_of); UP(o->loc_of, loc_of);
   UP(o->sell_ptr, m->sell_ptr); UP(o->sell_row, m->sell_row); UP(o->sell_col, m->sell_col);
-  UP(o->sell_src, m->sell_src);
+  UP(o->sell_src, m->sell_src); UP(o->lrowptr, m->lrowptr); UP(o->lcol, m->lcol);
 #undef UP
   // subdomains of the learned correction (unavailable with more than 32 regions)
   std::vector<int32_t> sub_ptr;
@@ -481,6 +489,8 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   launch_scale_rows(o->n, o->rowptr, o->col, o->val, o->s, s);
   launch_scale_w(o->ne, o->wrowptr, o->wval, o->s, s);
   launch_permute_r(o->nnzw, o->wtperm, o->wval, o->wtval, s);
+  launch_lap_assemble(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->edges, o->s, o->lrowptr, o->lcol, o->lval, s);
+  launch_lap_diag(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->edges, o->s, o->ldiag, s);
   launch_block_invert(o->nb, o->blk_ptr, o->blk_dofs, o->blk_of, o->loc_of, o->rowptr, o->col, o->val, o->ne,
                       o->wrowptr, o->wcol, o->wval, o->d0taup, o->gscr, o->minv, o->status, s);
   launch_to_c64(o->nnz, o->val, o->val32, s);
@@ -592,8 +602,7 @@ struct SolveWs {
   float2 *V32, *w32, *z32;   // complex64 inner loop (precision = 1)
   double *rpart, *nrm;
   // Coulomb projection (nodal CG)
-  double2 *psi, *cr, *cz, *cp, *cq, *cg, *cs;
-  double* cdiag;
+  double2 *psi, *cr, *cz, *cp, *cq, *cs;
   // device Hessenberg least squares
   double2 *Hd, *snd, *gd;
   double *csd, *est;
@@ -627,9 +636,7 @@ size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t
   w->cz = c.take<double2>(nv);
   w->cp = c.take<double2>(nv);
   w->cq = c.take<double2>(nv);
-  w->cg = c.take<double2>(ne);
   w->cs = c.take<double2>(8);
-  w->cdiag = c.take<double>(nv);
   w->Hd = c.take<double2>((int64_t)(m + 1) * m);
   w->snd = c.take<double2>(m + 1);
   w->gd = c.take<double2>(m + 2);
@@ -667,8 +674,7 @@ namespace {
 
 // Buffers of the post-solve steps (projection CG and residual check).
 struct ProjBufs {
-  double2 *psi, *cr, *cz, *cp, *cq, *cg, *cs;
-  double* cdiag;
+  double2 *psi, *cr, *cz, *cp, *cq, *cs;
   double2* part;
   double *rpart, *nrm;
   double2 *xtmp, *wtmp;   // n-vectors; xtmp may alias xt (consumed first)
@@ -693,27 +699,22 @@ eddy_status finish_solution(eddy_op* o, const ProjBufs& P, const double2* xt, co
   if (!gauge_op && bnorm > 0) {
     const int64_t nv = o->nv;
     launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, xt, P.cr, s);
-    launch_lap_diag(nv, o->wtrowptr, o->wtcol, o->wtval, o->edges, o->s, P.cdiag, s);
     launch_zero(nv, P.psi, s);
     launch_norm2(nv, P.cr, P.rpart, P.nrm, s);
     double r0 = 0;
     if ((st = read_norm(&r0)) != EDDY_OK) return st;
     if (r0 > 0) {
-      launch_jacobi(nv, P.cr, P.cdiag, P.cz, s);
+      // Jacobi-preconditioned CG on the assembled nodal operator L = W^T G
+      launch_jacobi(nv, P.cr, o->ldiag, P.cz, s);
       HIP_TRY(hipMemcpyAsync(P.cp, P.cz, sizeof(double2) * nv, hipMemcpyDeviceToDevice, s));
       launch_mdot(nv, P.cr, nv, 1, P.cz, P.part, s);
       launch_reduce_cols(1, mdot_parts(nv), P.part, P.cs + 0, s);
       int cur = 0;
       const int kMaxCg = 20000;
       for (int ci = 1; ci <= kMaxCg; ++ci) {
-        launch_grad_scaled(o->ne, o->edges, P.cp, o->s, P.cg, s);
-        launch_wt(nv, o->wtrowptr, o->wtcol, o->wtval, nullptr, P.cg, P.cq, s);
-        launch_mdot(nv, P.cp, nv, 1, P.cq, P.part, s);
-        launch_reduce_cols(1, mdot_parts(nv), P.part, P.cs + 2, s);
-        launch_cg_step(nv, P.cs + cur, P.cs + 2, P.cp, P.cq, P.psi, P.cr, s);
-        launch_jacobi(nv, P.cr, P.cdiag, P.cz, s);
-        launch_mdot(nv, P.cr, nv, 1, P.cz, P.part, s);
-        launch_reduce_cols(1, mdot_parts(nv), P.part, P.cs + (1 - cur), s);
+        launch_lap_spmv_dot(nv, o->lrowptr, o->lcol, o->lval, P.cp, P.cq, P.part, P.cs + 2, s);
+        launch_cg_update(nv, P.cs + cur, P.cs + 2, P.cp, P.cq, o->ldiag, P.psi, P.cr, P.cz, P.part,
+                         P.cs + (1 - cur), s);
         launch_cg_dir(nv, P.cs + (1 - cur), P.cs + cur, P.cz, P.cp, s);
         cur = 1 - cur;
         R.cg_iters = ci;
@@ -989,7 +990,7 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   } else {
     R.relres = 0;
   }
-  ProjBufs P{W.psi, W.cr, W.cz, W.cp, W.cq, W.cg, W.cs, W.cdiag, W.part, W.rpart, W.nrm, W.xt, W.w};
+  ProjBufs P{W.psi, W.cr, W.cz, W.cp, W.cq, W.cs, W.part, W.rpart, W.nrm, W.xt, W.w};
   if ((st = finish_solution(o, P, W.xt, W.bt, (double2*)x_dev, bnorm, gauge_op, R, s)) != EDDY_OK) return st;
   // remove the mass-weighted V mean per conductor component
   launch_vmean(o->nc, o->ncomp, o->comp, o->lumped, (double2*)x_dev + o->ne, o->red, s);
@@ -1061,9 +1062,7 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
   P.cz = c.take<double2>(nv);
   P.cp = c.take<double2>(nv);
   P.cq = c.take<double2>(nv);
-  P.cg = c.take<double2>(ne);
   P.cs = c.take<double2>(8);
-  P.cdiag = c.take<double>(nv);
   P.part = B->part;
   P.rpart = B->rpart;
   P.nrm = c.take<double>(8);

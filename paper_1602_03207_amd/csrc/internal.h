@@ -94,6 +94,8 @@ struct eddy_mesh {
   // W (ne x nv): pattern and scatter lists into wbuf; W^T via a permutation
   std::vector<int32_t> wrowptr, wcol, wcptr, wclist;
   std::vector<int32_t> wtrowptr, wtcol, wtperm;
+  // L = W^T G (nodal, symmetric; the Coulomb projection's operator): pattern
+  std::vector<int32_t> lrowptr, lcol;
   // gathers of vol4 (D0 over all tets, lumped conductor mass) and of rbuf
   std::vector<int32_t> d0ptr, d0list, lcptr, lclist, rptr, rlist;
   // sliced ELL: sell_ptr[nslices+1] (entry offsets), sell_row[nslices*kSellC]

@@ -151,10 +151,16 @@ void launch_edge_divergence(int64_t nv, const int* wtrowptr, const int* wtcol, c
                             double2* d, hipStream_t st);
 void launch_lap_diag(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const int* edges,
                      const double* s, double* diag, hipStream_t st);
-void launch_grad_scaled(int64_t ne, const int* edges, const double2* psi, const double* s, double2* g,
-                        hipStream_t st);
-void launch_cg_step(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q, double2* psi,
-                    double2* r, hipStream_t st);
+// L = W^T G assembled per node row; fused CG pieces: q = L p with p^H q (into
+// pq), and the update psi, r, z = r / diag with r^H z (into rz_new);
+// partial: kRedBlocks double2
+void launch_lap_assemble(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const int* edges,
+                         const double* s, const int* lrowptr, const int* lcol, double* lval, hipStream_t st);
+void launch_lap_spmv_dot(int64_t nv, const int* lrowptr, const int* lcol, const double* lval, const double2* p,
+                         double2* q, double2* partial, double2* pq, hipStream_t st);
+void launch_cg_update(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q,
+                      const double* diag, double2* psi, double2* r, double2* z, double2* partial, double2* rz_new,
+                      hipStream_t st);
 void launch_jacobi(int64_t n, const double2* r, const double* diag, double2* z, hipStream_t st);
 void launch_cg_dir(int64_t n, const double2* rz_new, const double2* rz_old, const double2* z, double2* p,
                    hipStream_t st);

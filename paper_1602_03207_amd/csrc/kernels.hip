@@ -460,28 +460,80 @@ __global__ __launch_bounds__(kThreads) void k_lap_diag(int64_t nv, const int* __
   diag[n] = acc;
 }
 
-// g_e = (psi_hi - psi_lo) / s_e  (gradient, pre-divided for the scaled W~^T)
-__global__ __launch_bounds__(kThreads) void k_grad_scaled(int64_t ne, const int* __restrict__ edges,
-                                                          const double2* __restrict__ psi,
-                                                          const double* __restrict__ s, double2* __restrict__ g) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
-  const double2 d = csub(psi[edges[2 * e + 1]], psi[edges[2 * e]]);
-  const double f = 1.0 / s[e];
-  g[e] = make_double2(d.x * f, d.y * f);
+// L = W^T G row by row (one thread per node, fixed order): the entry for
+// edge e in row n of W~^T (value s_e W_en) adds W_en at the edge's head and
+// subtracts it at its tail.
+__global__ __launch_bounds__(kThreads) void k_lap_assemble(int64_t nv, const int* __restrict__ wtrowptr,
+                                                           const int* __restrict__ wtcol,
+                                                           const double* __restrict__ wtval,
+                                                           const int* __restrict__ edges,
+                                                           const double* __restrict__ s,
+                                                           const int* __restrict__ lrowptr,
+                                                           const int* __restrict__ lcol, double* __restrict__ lval) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nv) return;
+  const int l0 = lrowptr[n], l1 = lrowptr[n + 1];
+  for (int p = l0; p < l1; ++p) lval[p] = 0.0;
+  for (int q = wtrowptr[n]; q < wtrowptr[n + 1]; ++q) {
+    const int e = wtcol[q];
+    const double f = wtval[q] / s[e];
+    const int lo = edges[2 * e], hi = edges[2 * e + 1];
+    for (int p = l0; p < l1; ++p) {
+      if (lcol[p] == hi) lval[p] += f;
+      if (lcol[p] == lo) lval[p] -= f;
+    }
+  }
 }
 
-// CG, step 1: alpha = rz / (p^H q); psi += alpha p; r -= alpha q   (rz, pq real parts on device)
-__global__ __launch_bounds__(kThreads) void k_cg_step(int64_t n, const double2* __restrict__ rz,
-                                                      const double2* __restrict__ pq, const double2* __restrict__ p,
-                                                      const double2* __restrict__ q, double2* __restrict__ psi,
-                                                      double2* __restrict__ r) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Projection CG, fused: q = L p with per-block partial sums of p^H q
+// (grid-stride over rows, kLanes lanes per row).
+__global__ __launch_bounds__(kThreads) void k_lap_spmv_dot(int64_t nv, const int* __restrict__ lrowptr,
+                                                           const int* __restrict__ lcol,
+                                                           const double* __restrict__ lval,
+                                                           const double2* __restrict__ p, double2* __restrict__ q,
+                                                           double2* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x % kLanes;
+  double2 acc = make_double2(0.0, 0.0);
+  const int64_t rows_per = (int64_t)gridDim.x * (blockDim.x / kLanes);
+  for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes; row < nv; row += rows_per) {
+    double2 y = make_double2(0.0, 0.0);
+    for (int k = lrowptr[row] + lane; k < lrowptr[row + 1]; k += kLanes) y = rfma(lval[k], p[lcol[k]], y);
+    for (int o = kLanes / 2; o > 0; o >>= 1) {
+      y.x += __shfl_xor(y.x, o, kLanes);
+      y.y += __shfl_xor(y.y, o, kLanes);
+    }
+    if (lane == 0) {
+      q[row] = y;
+      acc = cfma_conj(p[row], y, acc);
+    }
+  }
+  const double re = block_sum(acc.x, sh), im = block_sum(acc.y, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(re, im);
+}
+
+// Projection CG, fused: alpha = rz / pq; psi += alpha p; r -= alpha q;
+// z = r / diag; per-block partial sums of r^H z.
+__global__ __launch_bounds__(kThreads) void k_cg_update(int64_t n, const double2* __restrict__ rz,
+                                                        const double2* __restrict__ pq, const double2* __restrict__ p,
+                                                        const double2* __restrict__ q, const double* __restrict__ diag,
+                                                        double2* __restrict__ psi, double2* __restrict__ r,
+                                                        double2* __restrict__ z, double2* __restrict__ partial) {
+  __shared__ double sh[4];
   const double den = pq[0].x;
   const double a = den != 0.0 ? rz[0].x / den : 0.0;
-  psi[i] = rfma(a, p[i], psi[i]);
-  r[i] = rfma(-a, q[i], r[i]);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    psi[i] = rfma(a, p[i], psi[i]);
+    const double2 ri = rfma(-a, q[i], r[i]);
+    r[i] = ri;
+    const double f = diag[i] != 0.0 ? 1.0 / diag[i] : 0.0;
+    const double2 zi = make_double2(ri.x * f, ri.y * f);
+    z[i] = zi;
+    acc = fma(ri.x, zi.x, fma(ri.y, zi.y, acc));
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(acc, 0.0);
 }
 
 // z = r / diag
@@ -1816,13 +1868,20 @@ void launch_lap_diag(int64_t nv, const int* wtrowptr, const int* wtcol, const do
                      const double* s, double* diag, hipStream_t st) {
   k_lap_diag<<<blocks_for(nv), kThreads, 0, st>>>(nv, wtrowptr, wtcol, wtval, edges, s, diag);
 }
-void launch_grad_scaled(int64_t ne, const int* edges, const double2* psi, const double* s, double2* g,
-                        hipStream_t st) {
-  k_grad_scaled<<<blocks_for(ne), kThreads, 0, st>>>(ne, edges, psi, s, g);
+void launch_lap_assemble(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const int* edges,
+                         const double* s, const int* lrowptr, const int* lcol, double* lval, hipStream_t st) {
+  k_lap_assemble<<<blocks_for(nv), kThreads, 0, st>>>(nv, wtrowptr, wtcol, wtval, edges, s, lrowptr, lcol, lval);
 }
-void launch_cg_step(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q, double2* psi,
-                    double2* r, hipStream_t st) {
-  k_cg_step<<<blocks_for(n), kThreads, 0, st>>>(n, rz, pq, p, q, psi, r);
+void launch_lap_spmv_dot(int64_t nv, const int* lrowptr, const int* lcol, const double* lval, const double2* p,
+                         double2* q, double2* partial, double2* pq, hipStream_t st) {
+  k_lap_spmv_dot<<<kRedBlocks, kThreads, 0, st>>>(nv, lrowptr, lcol, lval, p, q, partial);
+  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, kRedBlocks, pq, nullptr, 0, 0, nullptr);
+}
+void launch_cg_update(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q,
+                      const double* diag, double2* psi, double2* r, double2* z, double2* partial, double2* rz_new,
+                      hipStream_t st) {
+  k_cg_update<<<kRedBlocks, kThreads, 0, st>>>(n, rz, pq, p, q, diag, psi, r, z, partial);
+  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, kRedBlocks, rz_new, nullptr, 0, 0, nullptr);
 }
 void launch_jacobi(int64_t n, const double2* r, const double* diag, double2* z, hipStream_t st) {
   k_jacobi<<<blocks_for(n), kThreads, 0, st>>>(n, r, diag, z);

@@ -357,6 +357,26 @@ eddy_status build_mesh(eddy_mesh* m) {
       for (int32_t p = m->wrowptr[r]; p < m->wrowptr[r + 1]; ++p) rowof[p] = (int32_t)r;
     for (size_t q = 0; q < m->wtperm.size(); ++q) m->wtcol[q] = rowof[m->wtperm[q]];
   }
+  // ---- pattern of L = W^T G: row n couples the endpoints of the edges in row n of W^T
+  {
+    m->lrowptr.assign(nv + 1, 0);
+    std::vector<std::vector<int32_t>> rows(nv);
+    parallel_chunks(nv, [&](int, int64_t a, int64_t b) {
+      for (int64_t n = a; n < b; ++n) {
+        auto& r = rows[n];
+        for (int32_t q = m->wtrowptr[n]; q < m->wtrowptr[n + 1]; ++q) {
+          const int32_t e = m->wtcol[q];
+          r.push_back(m->edges[2 * e]);
+          r.push_back(m->edges[2 * e + 1]);
+        }
+        std::sort(r.begin(), r.end());
+        r.erase(std::unique(r.begin(), r.end()), r.end());
+      }
+    });
+    for (int64_t n = 0; n < nv; ++n) m->lrowptr[n + 1] = m->lrowptr[n] + (int32_t)rows[n].size();
+    m->lcol.resize(m->lrowptr[nv]);
+    for (int64_t n = 0; n < nv; ++n) std::copy(rows[n].begin(), rows[n].end(), m->lcol.begin() + m->lrowptr[n]);
+  }
   // ---- D0 (all tets), lumped conductor mass (conducting tets), rhs gathers
   {
     std::vector<int32_t> item;
