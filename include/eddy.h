@@ -74,7 +74,9 @@ typedef struct {
   int32_t precision;   /* 0: FP64 throughout.  1: mixed -- each cycle's Krylov     */
                        /* process (SpMV, block-Jacobi apply, CGS2, basis) runs in  */
                        /* complex64; cycle residual, Hessenberg least squares,     */
-                       /* solution update and final residual stay FP64            */
+                       /* solution update and final residual stay FP64.  2: as 1, */
+                       /* with the block-Jacobi inverses stored in complex half   */
+                       /* precision (IEEE binary16 parts, float32 arithmetic)     */
   const float* gnn_theta;  /* NULL: plain block-Jacobi.  Otherwise the device      */
                            /* parameters (EDDY_GNN_PARAMS floats) of the learned    */
                            /* coarse correction, applied inside flexible GMRES     */

@@ -76,6 +76,7 @@ struct eddy_op {
   double2 *val, *ebuf, *minv;
   double* gscr;                 // gauge part of the diagonal blocks (assembly scratch)
   float2 *val32, *minv32;       // complex64 copies for the mixed-precision inner loop
+  uint32_t* minv16;             // complex-half block inverses (precision 2)
   double2* sval;                // sliced ELL values (complex128 and complex64)
   float2* sval32;
   // learned coarse correction: subdomain ranges in the block DOF list,
@@ -164,6 +165,7 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->gscr = c.take<double>(nb * kMaxBlock * kMaxBlock);
   o->val32 = c.take<float2>(m->nnz());
   o->minv32 = c.take<float2>(nb * kMaxBlock * kMaxBlock);
+  o->minv16 = c.take<uint32_t>(nb * kMaxBlock * kMaxBlock);
   o->wval = c.take<double>(m->nnzw());
   o->wtval = c.take<double>(m->nnzw());
   o->wbuf = c.take<double>(24 * m->nt);
@@ -495,6 +497,7 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
                       o->wrowptr, o->wcol, o->wval, o->d0taup, o->gscr, o->minv, o->status, s);
   launch_to_c64(o->nnz, o->val, o->val32, s);
   launch_to_c64(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv32, s);
+  launch_to_c16(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv16, s);
   launch_sell_gather(o->nsell, o->sell_src, o->val, o->sval, o->sval32, s);
   HIP_TRY(hipGetLastError());
   int stat = 0;
@@ -599,7 +602,7 @@ eddy_status eddy_export(const eddy_op* o, int32_t* rowptr, int32_t* col, eddy_c1
 namespace {
 struct SolveWs {
   double2 *V, *w, *z, *xt, *bt, *yd, *part;
-  float2 *V32, *w32, *z32;   // complex64 inner loop (precision = 1)
+  float2 *V32, *w32, *z32;   // complex64 inner loop (precision 1, 2)
   double *rpart, *nrm;
   // Coulomb projection (nodal CG)
   double2 *psi, *cr, *cz, *cp, *cq, *cs;
@@ -622,7 +625,7 @@ inline int64_t basis_ld(int64_t n) { return (n + 63) / 64 * 64; }   // 512-B ali
 size_t carve_solve(SolveWs* w, void* base, int64_t n, int m, int64_t nv, int64_t ne, int precision,
                    bool learned = false) {
   Carve c(base);
-  const bool mixed = precision == 1;
+  const bool mixed = precision >= 1;
   w->Z = c.take<double2>(learned && !mixed ? (int64_t)m * basis_ld(n) : 0);
   w->Z32 = c.take<float2>(learned && mixed ? (int64_t)m * basis_ld(n) : 0);
   w->gscr = c.take<float>(learned ? kGnnScratch : 0);
@@ -663,7 +666,10 @@ eddy_status check_opts(const eddy_solve_opts* p) {
   if (p->restart < 1 || p->restart > kMaxRestart) { set_error("restart must be in 1..64"); return EDDY_ERR_ARG; }
   if (p->max_iter < 1) { set_error("max_iter must be >= 1"); return EDDY_ERR_ARG; }
   if (!(p->tol > 0)) { set_error("tol must be > 0"); return EDDY_ERR_ARG; }
-  if (p->precision != 0 && p->precision != 1) { set_error("precision must be 0 (fp64) or 1 (mixed)"); return EDDY_ERR_ARG; }
+  if (p->precision < 0 || p->precision > 2) {
+    set_error("precision must be 0 (fp64), 1 (mixed) or 2 (mixed, half-precision block inverses)");
+    return EDDY_ERR_ARG;
+  }
   return EDDY_OK;
 }
 }  // namespace
@@ -747,7 +753,20 @@ struct Inner {
   const T* sval;     // sliced ELL values
   const T* minv;
   T* Z;              // preconditioned basis of the learned (flexible) cycles, or null
+  const uint32_t* minv16;   // complex-half block inverses (precision 2), or null
 };
+
+// z = blockdiag(M~)^-1 r with the inverses of the inner precision
+template <class T>
+void inner_block_apply(const eddy_op* o, const Inner<T>& I, const T* r, T* z, hipStream_t s) {
+  if constexpr (std::is_same<T, float2>::value) {
+    if (I.minv16) {
+      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv16, r, z, s);
+      return;
+    }
+  }
+  launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, r, z, s);
+}
 
 // Restarted right-preconditioned GMRES(m) with CGS2.  x~ (W.xt) starts at
 // zero, b~ = W.bt with ||b~|| = bnorm.  Returns with W.xt updated.
@@ -793,7 +812,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       hipEvent_t* ev = o->ev + 5 * ((j % kCheckEvery));
       T* zj = learned ? I.Z + (int64_t)j * ld : I.z;
       if (o->profile) (void)hipEventRecord(ev[0], s);
-      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, vj, zj, s);
+      inner_block_apply(o, I, (const T*)vj, zj, s);
       if (learned) {   // z_j += sum_p c_p (z_j on subdomain p), c from the network
         launch_gnn_stats(o->blk_dofs, o->sub_ptr, (const T*)vj, (const T*)zj, (const T*)nullptr, (const T*)nullptr,
                          nullptr, nullptr, o->gnn_part, o->gnn_sums, s);
@@ -872,7 +891,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       launch_combine(n, (const T*)I.Z, ld, k, W.yd, I.z, s);
     } else {
       launch_combine(n, (const T*)I.V, ld, k, W.yd, I.w, s);
-      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, (const T*)I.w, I.z, s);
+      inner_block_apply(o, I, (const T*)I.w, I.z, s);
     }
     launch_axpy(n, (const T*)I.z, W.xt, s);
     // FP64 true residual of the iterated operator: r = b~ - M~ x~
@@ -976,14 +995,14 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   // FP64 outer loop: the cycle residual r = b~ - M~ x~, the Hessenberg least
   // squares and the update of x~ are FP64; the Krylov process of each cycle
   // (SpMV, block-Jacobi apply, CGS2, basis) runs in the inner storage type.
-  const bool mixed = opts->precision == 1 && !gauge_op;
-  R.precision_used = mixed ? 1 : 0;
+  const bool mixed = opts->precision >= 1 && !gauge_op;
+  R.precision_used = mixed ? opts->precision : 0;
   if (bnorm > 0) {
     if (mixed) {
-      Inner<float2> I{W.V32, W.w32, W.z32, o->sval32, o->minv32, W.Z32};
+      Inner<float2> I{W.V32, W.w32, W.z32, o->sval32, o->minv32, W.Z32, opts->precision == 2 ? o->minv16 : nullptr};
       st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
     } else {
-      Inner<double2> I{W.V, W.w, W.z, o->sval, o->minv, W.Z};
+      Inner<double2> I{W.V, W.w, W.z, o->sval, o->minv, W.Z, nullptr};
       st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
     }
     if (st != EDDY_OK) return st;
@@ -1026,7 +1045,7 @@ struct BatchWs {
 size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, int precision) {
   Carve c(base);
   const int64_t n = o->n, ld = basis_ld(n), nv = o->nv, ne = o->ne;
-  const size_t tb = precision == 1 ? sizeof(float2) : sizeof(double2);
+  const size_t tb = precision >= 1 ? sizeof(float2) : sizeof(double2);
   B->nrhs = nrhs;
   B->m = m;
   B->ld = ld;
@@ -1086,6 +1105,16 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
   T* zT = (T*)B.zT;
   const T* val = std::is_same<T, float2>::value ? (const T*)o->val32 : (const T*)o->val;
   const T* minv = std::is_same<T, float2>::value ? (const T*)o->minv32 : (const T*)o->minv;
+  const bool half_inv = opts->precision == 2;
+  auto bapply = [&](int64_t rstride, const T* r, const int* act) {
+    if constexpr (std::is_same<T, float2>::value) {
+      if (half_inv) {
+        launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, o->minv16, nrhs, rstride, r, ld, zT, act, s);
+        return;
+      }
+    }
+    launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, rstride, r, ld, zT, act, s);
+  };
   std::vector<int> done(nrhs, 0), run(nrhs), cyc(nrhs), kc(nrhs);
   std::vector<double> beta(bnorm), est((size_t)nrhs * (m + 1));
   for (int r = 0; r < nrhs; ++r) done[r] = bnorm[r] > 0 ? 0 : 1;
@@ -1110,7 +1139,7 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     int jstart = 0;      // first estimate index not yet checked (common to the running systems)
     for (int j = 0; j < m; ++j) {
       T* vj = V + (int64_t)j * ld;
-      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, vstride, (const T*)vj, ld, zT, B.run, s);
+      bapply(vstride, (const T*)vj, B.run);
       launch_spmv_b(n, o->rowptr, o->col, val, nrhs, ld, (const T*)zT, (const T*)nullptr, wT, B.run, s);
       launch_mdot2_b(n, (const T*)V, ld, vstride, j, (const T*)vj, (const T*)wT, ld, B.part, pstride, B.run, nrhs, s);
       launch_reduce_cols_b(2 * j + 2, nparts2, B.part, pstride, B.dots, dstride, nullptr, B.run, nrhs, s);
@@ -1171,7 +1200,7 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     HIP_TRY(hipMemcpyAsync(B.kcols, kc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     launch_backsolve_b(B.kcols, m, B.Hd, B.gd, B.yd, hs, B.cyc, nrhs, s);
     launch_combine_b(n, (const T*)V, ld, vstride, B.kcols, B.yd, hs, wT, ld, B.cyc, nrhs, s);
-    launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, ld, (const T*)wT, ld, zT, B.cyc, s);
+    bapply(ld, (const T*)wT, B.cyc);
     launch_axpy_b(n, (const T*)zT, ld, B.xt, ld, B.cyc, nrhs, s);
     // FP64 true residuals of the penalty-free operator
     launch_spmv_b(n, o->rowptr, o->col, o->val, nrhs, ld, (const double2*)B.xt, (const double2*)B.bt, B.w64, B.cyc, s);
@@ -1249,7 +1278,7 @@ eddy_status eddy_solve_batched(eddy_op* o, int32_t nrhs, const eddy_c128* b_dev,
   launch_norm2_b(n, (const double2*)B.bt, ld, B.rpart, B.nrm, nullptr, nrhs, s);
   HIP_TRY(hipMemcpyAsync(bnorm.data(), B.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (opts->precision == 1) st = run_batched<float2>(o, B, opts, bnorm, its, R, s);
+  if (opts->precision >= 1) st = run_batched<float2>(o, B, opts, bnorm, its, R, s);
   else st = run_batched<double2>(o, B, opts, bnorm, its, R, s);
   if (st != EDDY_OK) return st;
   bool all = true;

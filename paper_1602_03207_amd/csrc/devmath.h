@@ -62,6 +62,24 @@ __device__ __forceinline__ float2 ld_stream(const float2* p) {
   return make_float2(v.x, v.y);
 }
 
+// Complex half precision (block inverses of the mixed16 mode): real part in
+// the low 16 bits, imaginary part in the high 16 bits, IEEE binary16 each.
+__device__ __forceinline__ uint32_t ld_stream(const uint32_t* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float2 unpack_h2(uint32_t b) {
+  const _Float16 lo = __builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
+  const _Float16 hi = __builtin_bit_cast(_Float16, (unsigned short)(b >> 16));
+  return make_float2((float)lo, (float)hi);
+}
+__device__ __forceinline__ uint32_t pack_h2(double re, double im) {
+  const unsigned short lo = __builtin_bit_cast(unsigned short, (_Float16)re);
+  const unsigned short hi = __builtin_bit_cast(unsigned short, (_Float16)im);
+  return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+// a stored matrix entry as a vector of the arithmetic type
+__device__ __forceinline__ double2 as_vec(double2 v) { return v; }
+__device__ __forceinline__ float2 as_vec(float2 v) { return v; }
+__device__ __forceinline__ float2 as_vec(uint32_t v) { return unpack_h2(v); }
+
 // ---- storage-type helpers: complex128 (double2) or complex64 (float2) ----
 __device__ __forceinline__ double2 ld2(double2 a) { return a; }
 __device__ __forceinline__ double2 ld2(float2 a) { return make_double2(a.x, a.y); }

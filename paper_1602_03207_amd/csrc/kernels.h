@@ -49,9 +49,12 @@ void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, 
 int spmv_full_grid(int64_t ns);
 void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2* sval, float2* sval32,
                         hipStream_t st);
-template <class T>
-void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, const T* r, T* z,
+// MT: storage of the inverses, T or (with T = float2) packed complex half (uint32_t)
+template <class T, class MT>
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const T* r, T* z,
                         hipStream_t st);
+// complex128 -> packed complex half (round to nearest even)
+void launch_to_c16(int64_t n, const double2* in, uint32_t* out, hipStream_t st);
 // Krylov primitives: storage T, all reductions and Hessenberg entries in FP64
 // partial dots V^H w (+ ||w||^2 in slot q if want_norm); flag (device, may be
 // null) = 0 skips the launch
@@ -75,8 +78,8 @@ void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st);
 void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
 // ---- batched systems (vectors of system r at offset r * stride; grid.z = r;
 // `active` (device int[nrhs], may be null) masks systems out)
-template <class T>
-void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, int nrhs,
+template <class T, class MT>
+void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, int nrhs,
                           int64_t rstride, const T* r, int64_t zstride, T* z, const int* active, hipStream_t st);
 template <class T>
 void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, int nrhs, int64_t ld, const T* x,

@@ -652,11 +652,12 @@ __global__ __launch_bounds__(kThreads) void k_sell_gather(int64_t tot, const int
   sval32[i] = make_float2((float)v.x, (float)v.y);
 }
 
-// z_I = Minv_I r_I, one 64-lane wavefront per block, 4 blocks per workgroup.
-template <class T>
+// z_I = Minv_I r_I, one 64-lane wavefront per block, 4 blocks per workgroup;
+// MT the storage of the inverses (T, or packed complex half with T = float2).
+template <class T, class MT>
 __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int* __restrict__ blk_ptr,
                                                           const int* __restrict__ blk_dofs,
-                                                          const T* __restrict__ minv, const T* __restrict__ r,
+                                                          const MT* __restrict__ minv, const T* __restrict__ r,
                                                           T* __restrict__ z) {
   __shared__ T rl[4][kMaxBlock];
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
@@ -670,9 +671,9 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int*
   rl[w][i] = dof >= 0 ? r[dof] : zero2<T>();
   __syncthreads();
   if (dof < 0) return;
-  const T* Mk = minv + k * kMaxBlock * kMaxBlock;
+  const MT* Mk = minv + k * kMaxBlock * kMaxBlock;
   T acc = zero2<T>();
-  for (int j = 0; j < sz; ++j) acc = cfmaT(ld_stream(Mk + j * kMaxBlock + i), rl[w][j], acc);
+  for (int j = 0; j < sz; ++j) acc = cfmaT(as_vec(ld_stream(Mk + j * kMaxBlock + i)), rl[w][j], acc);
   z[dof] = acc;
 }
 
@@ -1248,10 +1249,10 @@ __global__ void k_backsolve_b(const int* __restrict__ ks, int m, const double2* 
 // per launch for up to kBatchChunk systems (vectors of system r at r * ld).
 
 // z_r = Minv r_r for the active systems, one wavefront per block.
-template <class T>
+template <class T, class MT>
 __global__ __launch_bounds__(kThreads) void k_block_apply_b(int64_t nb, const int* __restrict__ blk_ptr,
                                                             const int* __restrict__ blk_dofs,
-                                                            const T* __restrict__ minv, int nrhs, int64_t rstride,
+                                                            const MT* __restrict__ minv, int nrhs, int64_t rstride,
                                                             const T* __restrict__ r, int64_t zstride,
                                                             T* __restrict__ z, const int* __restrict__ active) {
   __shared__ T rl[4][kBatchChunk][kMaxBlock];
@@ -1263,7 +1264,7 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_b(int64_t nb, const in
     sz = blk_ptr[k + 1] - b0;
     if (i < sz) dof = blk_dofs[b0 + i];
   }
-  const T* Mk = minv + k * kMaxBlock * kMaxBlock;
+  const MT* Mk = minv + k * kMaxBlock * kMaxBlock;
   for (int c0 = 0; c0 < nrhs; c0 += kBatchChunk) {
     const int cn = min(kBatchChunk, nrhs - c0);
 #pragma unroll
@@ -1277,7 +1278,7 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_b(int64_t nb, const in
 #pragma unroll
       for (int q = 0; q < kBatchChunk; ++q) acc[q] = zero2<T>();
       for (int j = 0; j < sz; ++j) {
-        const T mij = Mk[j * kMaxBlock + i];
+        const T mij = as_vec(ld_stream(Mk + j * kMaxBlock + i));
 #pragma unroll
         for (int q = 0; q < kBatchChunk; ++q)
           if (q < cn) acc[q] = cfmaT(mij, rl[w][q][j], acc[q]);
@@ -1620,10 +1621,10 @@ void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2
                         hipStream_t st) {
   k_sell_gather<<<blocks_for(tot), kThreads, 0, st>>>(tot, src, val, sval, sval32);
 }
-template <class T>
-void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, const T* r, T* z,
+template <class T, class MT>
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const T* r, T* z,
                         hipStream_t st) {
-  k_block_apply<T><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
+  k_block_apply<T, MT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
 }
 int mdot2_parts(int64_t n) {
   const int64_t tiles = (n + kDot2Rows - 1) / kDot2Rows;
@@ -1723,10 +1724,10 @@ void launch_backsolve(int k, int m, const double2* H, const double2* g, double2*
   k_backsolve<<<1, 64, 0, st>>>(k, m, H, g, y);
 }
 // ---- batched launch wrappers (grid.z = system index)
-template <class T>
-void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const T* minv, int nrhs,
+template <class T, class MT>
+void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, int nrhs,
                           int64_t rstride, const T* r, int64_t zstride, T* z, const int* active, hipStream_t st) {
-  k_block_apply_b<T><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, nrhs, rstride, r, zstride,
+  k_block_apply_b<T, MT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, nrhs, rstride, r, zstride,
                                                               z, active);
 }
 template <class T>
@@ -1794,7 +1795,7 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   template void launch_spmv<T>(int64_t, const int*, const int*, const int*, const T*, int64_t, const int*,       \
                                const int*, const double*, const double2*, const T*, const double2*, T*,          \
                                hipStream_t, int, int);                                                           \
-  template void launch_block_apply<T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t);      \
+  template void launch_block_apply<T, T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t);   \
   template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t, int, const int*); \
   template void launch_norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                \
   template void launch_scale_by_inv<T>(int64_t, const T*, const double*, T*, hipStream_t);                        \
@@ -1823,8 +1824,8 @@ template void launch_dcgs_update_b<float2>(int64_t, const float2*, int64_t, int6
                                            float2*, float2*, int64_t, double*, double*, const int*, int,
                                            hipStream_t);
 #define EDDY_INST_B(T)                                                                                            \
-  template void launch_block_apply_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, int64_t, \
-                                        T*, const int*, hipStream_t);                                             \
+  template void launch_block_apply_b<T, T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*,     \
+                                           int64_t, T*, const int*, hipStream_t);                                 \
   template void launch_spmv_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, const T*, T*,  \
                                  const int*, hipStream_t);                                                        \
   template void launch_norm2_b<T>(int64_t, const T*, int64_t, double*, double*, const int*, int, hipStream_t);      \
@@ -1837,6 +1838,18 @@ template void launch_dcgs_update_b<float2>(int64_t, const float2*, int64_t, int6
 EDDY_INST_B(double2)
 EDDY_INST_B(float2)
 #undef EDDY_INST_B
+template void launch_block_apply<float2, uint32_t>(int64_t, const int*, const int*, const uint32_t*, const float2*,
+                                                   float2*, hipStream_t);
+template void launch_block_apply_b<float2, uint32_t>(int64_t, const int*, const int*, const uint32_t*, int, int64_t,
+                                                     const float2*, int64_t, float2*, const int*, hipStream_t);
+__global__ __launch_bounds__(kThreads) void k_to_c16(int64_t n, const double2* __restrict__ in,
+                                                     uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = pack_h2(in[i].x, in[i].y);
+}
+void launch_to_c16(int64_t n, const double2* in, uint32_t* out, hipStream_t st) {
+  k_to_c16<<<blocks_for(n), kThreads, 0, st>>>(n, in, out);
+}
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st) {
   k_diag_scale<<<blocks_for(n), kThreads, 0, st>>>(n, in, s, divide, out, 0, 0);
 }

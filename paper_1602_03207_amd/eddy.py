@@ -306,13 +306,14 @@ class Operator:
         return b
 
     def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64", gnn_theta=None):
-        """precision: "fp64", or "mixed" (complex64 Krylov process, FP64 outer residual).
+        """precision: "fp64", "mixed" (complex64 Krylov process, FP64 outer residual), or
+        "mixed16" (as mixed, with complex-half block-Jacobi inverses).
         gnn_theta: float32 device tensor of EDDY_GNN_PARAMS network parameters
         (the learned coarse correction with fallback), or None."""
         if gnn_theta is not None:
             assert gnn_theta.dtype.is_floating_point and gnn_theta.element_size() == 4 and gnn_theta.is_contiguous()
             assert gnn_theta.numel() == GNN_PARAMS
-        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1}[precision],
+        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1, "mixed16": 2}[precision],
                      None if gnn_theta is None else gnn_theta.data_ptr())
         nbytes = C.c_size_t()
         _check(_lib.eddy_solve_workspace_bytes(self._h, C.byref(opts), C.byref(nbytes)), "eddy_solve_workspace_bytes")
@@ -333,7 +334,7 @@ class Operator:
         import torch
         B = B.reshape(-1, self.ndof).contiguous()
         nrhs = B.shape[0]
-        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1}[precision])
+        opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1, "mixed16": 2}[precision])
         nbytes = C.c_size_t()
         _check(_lib.eddy_solve_batched_workspace_bytes(self._h, nrhs, C.byref(opts), C.byref(nbytes)),
                "eddy_solve_batched_workspace_bytes")

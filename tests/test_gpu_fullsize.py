@@ -166,6 +166,11 @@ def test_fullsize_solves_fp64_and_mixed():
     print(f"fp64 iters {r64.iters} ({r64.seconds:.2f} s), mixed iters {rmx.iters} ({rmx.seconds:.2f} s), "
           f"rel diff {err:.2e}")
     assert err <= 1e-5
+    x16, r16 = op.solve(b1, tol=1e-8, restart=30, max_iter=20000, precision="mixed16")
+    assert r16.converged and r16.relres <= 1e-8 and r16.precision_used == 2
+    err16 = (torch.linalg.norm(x16 - x64) / torch.linalg.norm(x64)).item()
+    print(f"mixed16 iters {r16.iters} ({r16.seconds:.2f} s), rel diff {err16:.2e}")
+    assert err16 <= 1e-5 and r16.iters <= 1.1 * rmx.iters
     x2, rr2 = op.solve(b2, tol=1e-8, restart=30, max_iter=20000, precision="mixed")
     assert rr2.converged
     Z = op.impedance(torch.stack([xmx, x2]), torch.stack([b1, b2]), [1.0, 1.0])

@@ -230,15 +230,17 @@ def test_gauge_modes_and_coulomb_projection():
     assert np.linalg.norm(x2.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
-def test_mixed_precision_c1_matches_oracle():
-    """complex64 Krylov process inside the FP64 outer residual: converges to
-    the FP64 tolerance on the true residual and matches the direct oracle."""
+@pytest.mark.parametrize("prec,code", [("mixed", 1), ("mixed16", 2)])
+def test_mixed_precision_c1_matches_oracle(prec, code):
+    """complex64 Krylov process (with complex64 or complex-half block
+    inverses) inside the FP64 outer residual: converges to the FP64 tolerance
+    on the true residual and matches the direct oracle."""
     from oracle.solve import direct
     from oracle.post import remove_v_mean
     m, s, op, J = case("c1")
     b = op.rhs_from_current(torch.from_numpy(J).cuda())
-    x, rep = op.solve(b, tol=1e-11, precision="mixed")
-    assert rep.converged and rep.precision_used == 1 and rep.relres <= 1e-11
+    x, rep = op.solve(b, tol=1e-11, precision=prec)
+    assert rep.converged and rep.precision_used == code and rep.relres <= 1e-11
     xo = remove_v_mean(s, direct(s, s.rhs(J)))
     err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
     assert err <= 1e-9, err
@@ -267,7 +269,7 @@ def test_tau_precond_changes_only_the_preconditioner():
     assert abs(rep10.iters - res.iters) <= max(2, 0.05 * res.iters)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed16"])
 def test_batched_solve_matches_single_solves(precision):
     """The batched solver runs the same GMRES per system: same iterations and
     the same solution as separate solves (and the oracle's direct solve)."""
