@@ -71,6 +71,7 @@ struct eddy_op {
   int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
   int *sell_ptr, *sell_row, *sell_col, *sell_src;
   int *lrowptr, *lcol;          // L = W^T G pattern (Coulomb projection)
+  int* xcd_groups;              // SpMV schedule 1: group ranges of equal stored entries per XCD
   int64_t nnzl;
   // numeric
   double2 *val, *ebuf, *minv;
@@ -155,6 +156,7 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->sell_src = c.take<int>(nsell);
   o->sval = c.take<double2>(nsell);
   o->sval32 = c.take<float2>(nsell);
+  o->xcd_groups = c.take<int>(16);
   o->lrowptr = c.take<int>(m->nv + 1);
   o->lcol = c.take<int>((int64_t)m->lcol.size());
   o->lval = c.take<double>((int64_t)m->lcol.size());
@@ -252,11 +254,11 @@ eddy_status tune_spmv(eddy_op* o, const T* sval, T* x, T* y, int* best_grid, int
     for (int g : caps) {
       if (g >= full) continue;
       launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, sval, o->ne, nullptr, nullptr, nullptr, nullptr, x,
-                  nullptr, y, s, g, sch);
+                  nullptr, y, s, g, sch, o->xcd_groups);
       (void)hipEventRecord(e0, s);
       for (int r = 0; r < reps; ++r)
         launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, sval, o->ne, nullptr, nullptr, nullptr, nullptr,
-                    x, nullptr, y, s, g, sch);
+                    x, nullptr, y, s, g, sch, o->xcd_groups);
       (void)hipEventRecord(e1, s);
       float ms = 0;
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -281,7 +283,7 @@ void op_spmv(const eddy_op* o, const double2* x, const double2* b, double2* y, d
              bool gauge = true) {
   if (gauge) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, x, t, st);
   launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, o->sval, o->ne, gauge ? o->wrowptr : nullptr, o->wcol,
-              o->wval, t, x, b, y, st, o->tune.spmv_grid_c128, o->tune.spmv_sched_c128);
+              o->wval, t, x, b, y, st, o->tune.spmv_grid_c128, o->tune.spmv_sched_c128, o->xcd_groups);
 }
 
 }  // namespace
@@ -433,6 +435,19 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   UP(o->blk_of, blk_of); UP(o->loc_of, loc_of);
   UP(o->sell_ptr, m->sell_ptr); UP(o->sell_row, m->sell_row); UP(o->sell_col, m->sell_col);
   UP(o->sell_src, m->sell_src); UP(o->lrowptr, m->lrowptr); UP(o->lcol, m->lcol);
+  {
+    // groups of 4 slices; XCD k starts at the first group whose entries reach k/8 of the total
+    const int64_t ns = (int64_t)m->sell_ptr.size() - 1, ng = (ns + 3) / 4;
+    const double tot = (double)m->sell_ptr[ns];
+    std::vector<int32_t> xg(9, 0);
+    int64_t g = 0;
+    for (int k = 1; k < 8; ++k) {
+      while (g < ng && (double)m->sell_ptr[std::min<int64_t>(4 * g, ns)] < tot * k / 8.0) ++g;
+      xg[k] = (int32_t)g;
+    }
+    xg[8] = (int32_t)ng;
+    UP(o->xcd_groups, xg);
+  }
 #undef UP
   // subdomains of the learned correction (unavailable with more than 32 regions)
   std::vector<int32_t> sub_ptr;
@@ -826,7 +841,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, I.sval, o->ne, gauge_op ? o->wrowptr : nullptr,
                   o->wcol, o->wval, o->tvec, (const T*)zj, nullptr, I.w, s,
                   std::is_same<T, float2>::value ? o->tune.spmv_grid_c64 : o->tune.spmv_grid_c128,
-                  std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128);
+                  std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128, o->xcd_groups);
       if (o->profile) (void)hipEventRecord(ev[3], s);
       launch_mdot2(n, (const T*)I.V, ld, j, (const T*)vj, (const T*)I.w, W.part, s);
       launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);

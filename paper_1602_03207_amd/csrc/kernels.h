@@ -40,11 +40,13 @@ void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* 
 // M~ in the sliced ELL layout (ns slices); T = double2 (complex128) or float2
 // (complex64) storage and arithmetic.  grid > 0 caps the number of
 // workgroups; schedule 0 sweeps the slices with all XCDs together, 1 gives
-// each XCD a contiguous range.  Neither changes the result.
+// each XCD a contiguous range of groups of 4 slices, xcd_groups[9] (device)
+// the range boundaries.  Neither changes the result.
 template <class T>
 void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, const T* sval, int64_t ne,
                  const int* wrowptr, const int* wcol, const double* wval, const double2* t, const T* x,
-                 const double2* b, T* y, hipStream_t st, int grid = 0, int schedule = 0);
+                 const double2* b, T* y, hipStream_t st, int grid = 0, int schedule = 0,
+                 const int* xcd_groups = nullptr);
 // workgroups of an uncapped SpMV launch over ns slices
 int spmv_full_grid(int64_t ns);
 void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2* sval, float2* sval32,

@@ -578,8 +578,9 @@ __global__ __launch_bounds__(kThreads) void k_project(int64_t ne, int64_t nc, co
 // wavefront.  Workgroups loop over groups of 4 slices.  Schedule 0: group g,
 // g + grid, ... (all XCDs sweep the rows together).  Schedule 1: workgroups
 // are dispatched round-robin over the kXcds XCDs (workgroup i on XCD i mod
-// kXcds), and each XCD takes a contiguous range of groups, so the rows
-// sharing gathered x entries stay under one L2.  Each row's sum has the same
+// kXcds), and each XCD takes a contiguous range of groups holding an equal
+// share of the stored entries (xcd_groups[kXcds + 1]), so the rows sharing
+// gathered x entries stay under one L2.  Each row's sum has the same
 // order in every schedule and grid size.
 constexpr int kXcds = 8;
 template <class T>
@@ -587,7 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* _
                                                         const int* __restrict__ srow, const int* __restrict__ scol,
                                                         const T* __restrict__ sval, const T* __restrict__ x,
                                                         const double2* __restrict__ b, T* __restrict__ y,
-                                                        int schedule) {
+                                                        int schedule, const int* __restrict__ xcd_groups) {
   static_assert(kSellC == 64, "one wavefront per slice");
   constexpr int kGroup = kThreads / 64;
   const int l = threadIdx.x & 63;
@@ -600,8 +601,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* _
   } else {
     const int64_t xcd = blockIdx.x % kXcds, q = blockIdx.x / kXcds;
     const int64_t nwg = gridDim.x / kXcds + (xcd < (int64_t)(gridDim.x % kXcds) ? 1 : 0);
-    g0 = ngroups * xcd / kXcds + q;
-    g1 = ngroups * (xcd + 1) / kXcds;
+    g0 = xcd_groups[xcd] + q;      // ranges of equal stored entries
+    g1 = xcd_groups[xcd + 1];
     gstep = nwg;
   }
   for (int64_t g = g0; g < g1; g += gstep) {
@@ -1608,11 +1609,11 @@ void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* 
 template <class T>
 void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, const T* sval, int64_t ne,
                  const int* wrowptr, const int* wcol, const double* wval, const double2* t, const T* x,
-                 const double2* b, T* y, hipStream_t st, int grid, int schedule) {
+                 const double2* b, T* y, hipStream_t st, int grid, int schedule, const int* xcd_groups) {
   const unsigned full = blocks_for(ns * kSellC);
   unsigned g = grid > 0 && (unsigned)grid < full ? (unsigned)grid : full;
-  if (schedule && g < (unsigned)kXcds) schedule = 0;
-  k_spmv_sell<T><<<g, kThreads, 0, st>>>(ns, sptr, srow, scol, sval, x, b, y, schedule);
+  if (schedule && (g < (unsigned)kXcds || !xcd_groups)) schedule = 0;
+  k_spmv_sell<T><<<g, kThreads, 0, st>>>(ns, sptr, srow, scol, sval, x, b, y, schedule, xcd_groups);
   if (wrowptr)
     k_gauge_add<T><<<blocks_for(ne * kLanes), kThreads, 0, st>>>(ne, wrowptr, wcol, wval, t, b ? -1.0 : 1.0, y);
 }
@@ -1794,7 +1795,7 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
 #define EDDY_INST(T)                                                                                              \
   template void launch_spmv<T>(int64_t, const int*, const int*, const int*, const T*, int64_t, const int*,       \
                                const int*, const double*, const double2*, const T*, const double2*, T*,          \
-                               hipStream_t, int, int);                                                           \
+                               hipStream_t, int, int, const int*);                                               \
   template void launch_block_apply<T, T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t);   \
   template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t, int, const int*); \
   template void launch_norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                \
