@@ -28,7 +28,7 @@ constexpr int kMaxBlock = 64;       // block-Jacobi block size limit (LDS-reside
 constexpr int kMaxRestart = 64;
 constexpr int kMaxWRow = 32;       // max nodes adjacent to one edge (LDS-staged gauge blocks)
 constexpr int kBatchChunk = 8;     // systems per pass of the batched SpMV / block-Jacobi kernels
-constexpr int kMaxDzCols = 4;
+constexpr int kMaxDzCols = 4;      // free-configuration solutions per pass of the defect-volume kernel
 // Learned coarse correction: a graph network on kGnnP subdomains, kGnnFin
 // input features, width kGnnWidth, kGnnFout outputs (the first two used).
 // Parameters (float32, in this order, row-major): W0 [Fin x W], b0 [W],
@@ -55,7 +55,7 @@ constexpr int kGnnScratch = 7 * kGnnP * kGnnWidth + kGnnP * kGnnFout +
 // one lane per row), rows sorted by decreasing length inside windows of
 // kSellWindow rows; slice s holds its width x kSellC entries column-major.
 constexpr int kSellC = 64;
-constexpr int kSellWindow = 1024;      // free-configuration solutions per pass of the defect-volume kernel
+constexpr int kSellWindow = 1024;
 
 inline int pair6(int l, int m) {    // upper-triangle slot of a symmetric 6x6
   if (l > m) { int t = l; l = m; m = t; }
