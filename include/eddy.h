@@ -75,8 +75,10 @@ typedef struct {
                        /* process (SpMV, block-Jacobi apply, CGS2, basis) runs in  */
                        /* complex64; cycle residual, Hessenberg least squares,     */
                        /* solution update and final residual stay FP64.  2: as 1, */
-                       /* with the block-Jacobi inverses stored in complex half   */
-                       /* precision (IEEE binary16 parts, float32 arithmetic)     */
+                       /* with the block-Jacobi inverses and the Krylov basis     */
+                       /* stored in complex half precision (IEEE binary16 parts;  */
+                       /* the unit basis vectors scaled by 2^14), float32         */
+                       /* arithmetic; with gnn_theta the basis stays complex64    */
   const float* gnn_theta;  /* NULL: plain block-Jacobi.  Otherwise the device      */
                            /* parameters (EDDY_GNN_PARAMS floats) of the learned    */
                            /* coarse correction, applied inside flexible GMRES     */

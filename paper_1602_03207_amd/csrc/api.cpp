@@ -760,9 +760,9 @@ eddy_status finish_solution(eddy_op* o, const ProjBufs& P, const double2* xt, co
   return EDDY_OK;
 }
 
-template <class T>
+template <class T, class VT = T>
 struct Inner {
-  T* V;
+  VT* V;             // Krylov basis (T, or complex half for precision 2)
   T* w;
   T* z;
   const T* sval;     // sliced ELL values
@@ -772,21 +772,26 @@ struct Inner {
 };
 
 // z = blockdiag(M~)^-1 r with the inverses of the inner precision
-template <class T>
-void inner_block_apply(const eddy_op* o, const Inner<T>& I, const T* r, T* z, hipStream_t s) {
-  if constexpr (std::is_same<T, float2>::value) {
-    if (I.minv16) {
-      launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv16, r, z, s);
-      return;
+template <class T, class VT, class RT>
+void inner_block_apply(const eddy_op* o, const Inner<T, VT>& I, const RT* r, T* z, hipStream_t s) {
+  if constexpr (std::is_same<RT, hbasis>::value) {
+    // the complex-half basis comes with the complex-half inverses (precision 2)
+    launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv16, r, z, s);
+  } else {
+    if constexpr (std::is_same<T, float2>::value) {
+      if (I.minv16) {
+        launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv16, r, z, s);
+        return;
+      }
     }
+    launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, r, z, s);
   }
-  launch_block_apply(o->nb, o->blk_ptr, o->blk_dofs, I.minv, r, z, s);
 }
 
 // Restarted right-preconditioned GMRES(m) with CGS2.  x~ (W.xt) starts at
 // zero, b~ = W.bt with ||b~|| = bnorm.  Returns with W.xt updated.
-template <class T>
-eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts* opts, bool gauge_op,
+template <class T, class VT>
+eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_opts* opts, bool gauge_op,
                       double bnorm, int& it, eddy_solve_report& R, hipStream_t s) {
   const int m = opts->restart;
   const int64_t n = o->n;
@@ -823,17 +828,19 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
     int k = 0, jstart = 0;     // jstart: first estimate index not yet checked
     bool stop = false;
     for (int j = 0; j < m; ++j) {
-      T* vj = I.V + (int64_t)j * ld;
+      VT* vj = I.V + (int64_t)j * ld;
       hipEvent_t* ev = o->ev + 5 * ((j % kCheckEvery));
       T* zj = learned ? I.Z + (int64_t)j * ld : I.z;
       if (o->profile) (void)hipEventRecord(ev[0], s);
-      inner_block_apply(o, I, (const T*)vj, zj, s);
-      if (learned) {   // z_j += sum_p c_p (z_j on subdomain p), c from the network
-        launch_gnn_stats(o->blk_dofs, o->sub_ptr, (const T*)vj, (const T*)zj, (const T*)nullptr, (const T*)nullptr,
-                         nullptr, nullptr, o->gnn_part, o->gnn_sums, s);
-        launch_gnn_features(o->gnn_sums, o->static4, 0, o->gnn_X, nullptr, nullptr, s);
-        launch_gnn_forward(1, theta, o->ahat, o->gnn_X, o->gnn_Y, W.gscr, s);
-        launch_gnn_scale(o->blk_dofs, o->sub_ptr, o->gnn_Y, zj, s);
+      inner_block_apply(o, I, (const VT*)vj, zj, s);
+      if constexpr (std::is_same<T, VT>::value) {
+        if (learned) {   // z_j += sum_p c_p (z_j on subdomain p), c from the network
+          launch_gnn_stats(o->blk_dofs, o->sub_ptr, (const T*)vj, (const T*)zj, (const T*)nullptr,
+                           (const T*)nullptr, nullptr, nullptr, o->gnn_part, o->gnn_sums, s);
+          launch_gnn_features(o->gnn_sums, o->static4, 0, o->gnn_X, nullptr, nullptr, s);
+          launch_gnn_forward(1, theta, o->ahat, o->gnn_X, o->gnn_Y, W.gscr, s);
+          launch_gnn_scale(o->blk_dofs, o->sub_ptr, o->gnn_Y, zj, s);
+        }
       }
       if (o->profile) (void)hipEventRecord(ev[1], s);
       if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, (const double2*)zj, o->tvec, s);
@@ -843,11 +850,11 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
                   std::is_same<T, float2>::value ? o->tune.spmv_grid_c64 : o->tune.spmv_grid_c128,
                   std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128, o->xcd_groups);
       if (o->profile) (void)hipEventRecord(ev[3], s);
-      launch_mdot2(n, (const T*)I.V, ld, j, (const T*)vj, (const T*)I.w, W.part, s);
+      launch_mdot2(n, (const VT*)I.V, ld, j, (const VT*)vj, (const T*)I.w, W.part, s);
       launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);
       launch_dcgs_coef(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est,
                        learned ? W.Sall : nullptr, learned ? W.rhoall : nullptr, s);
-      launch_dcgs_update(n, (const T*)I.V, ld, j, W.coef, vj, I.w, W.rpart, W.tnorm, s);
+      launch_dcgs_update(n, (const VT*)I.V, ld, j, W.coef, vj, I.w, W.rpart, W.tnorm, s);
       launch_scale_by_inv(n, (const T*)I.w, W.tnorm, I.V + (int64_t)(j + 1) * ld, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
       ++it;
@@ -905,7 +912,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T>& I, const eddy_solve_opts
       launch_flex_coeffs(k, m, W.Sall, W.rhoall, W.yd, s);
       launch_combine(n, (const T*)I.Z, ld, k, W.yd, I.z, s);
     } else {
-      launch_combine(n, (const T*)I.V, ld, k, W.yd, I.w, s);
+      launch_combine(n, (const VT*)I.V, ld, k, W.yd, I.w, s);
       inner_block_apply(o, I, (const T*)I.w, I.z, s);
     }
     launch_axpy(n, (const T*)I.z, W.xt, s);
@@ -1014,8 +1021,15 @@ eddy_status eddy_solve(eddy_op* o, const eddy_c128* b_dev, eddy_c128* x_dev, con
   R.precision_used = mixed ? opts->precision : 0;
   if (bnorm > 0) {
     if (mixed) {
-      Inner<float2> I{W.V32, W.w32, W.z32, o->sval32, o->minv32, W.Z32, opts->precision == 2 ? o->minv16 : nullptr};
-      st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
+      if (opts->precision == 2 && !opts->gnn_theta) {
+        // complex-half basis (same 4-byte footprint as the complex64 one)
+        Inner<float2, hbasis> I{(hbasis*)W.V32, W.w32, W.z32, o->sval32, o->minv32, W.Z32, o->minv16};
+        st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
+      } else {
+        Inner<float2> I{W.V32, W.w32, W.z32, o->sval32, o->minv32, W.Z32,
+                        opts->precision == 2 ? o->minv16 : nullptr};
+        st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
+      }
     } else {
       Inner<double2> I{W.V, W.w, W.z, o->sval, o->minv, W.Z, nullptr};
       st = run_gmres(o, W, I, opts, gauge_op, bnorm, it, R, s);
@@ -1064,7 +1078,8 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
   B->nrhs = nrhs;
   B->m = m;
   B->ld = ld;
-  B->V = c.take<char>((int64_t)nrhs * (m + 1) * ld * tb);
+  const size_t vb = precision == 2 ? sizeof(hbasis) : tb;     // complex-half basis at precision 2
+  B->V = c.take<char>((int64_t)nrhs * (m + 1) * ld * vb);
   B->wT = c.take<char>((int64_t)nrhs * ld * tb);
   B->zT = c.take<char>((int64_t)nrhs * ld * tb);
   B->xt = c.take<double2>((int64_t)nrhs * ld);
@@ -1107,7 +1122,8 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
 
 // Independent GMRES(m) processes for nrhs systems in lockstep cycles; the
 // SpMV and block-Jacobi launches serve every active system at once.
-template <class T>
+// VT: storage of the basis (T, or hbasis with T = float2)
+template <class T, class VT>
 eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std::vector<double>& bnorm,
                         std::vector<int>& its, std::vector<eddy_solve_report>& R, hipStream_t s) {
   const int nrhs = B.nrhs, m = B.m;
@@ -1115,20 +1131,25 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
   const int64_t np = mdot_parts(n > o->nv ? n : o->nv);
   const int64_t pstride = std::max<int64_t>(np * (m + 2), (int64_t)mdot2_parts(n) * (2 * m + 2));
   const int64_t dstride = 2 * kMaxRestart + 4;
-  T* V = (T*)B.V;
+  VT* V = (VT*)B.V;
   T* wT = (T*)B.wT;
   T* zT = (T*)B.zT;
   const T* val = std::is_same<T, float2>::value ? (const T*)o->val32 : (const T*)o->val;
   const T* minv = std::is_same<T, float2>::value ? (const T*)o->minv32 : (const T*)o->minv;
   const bool half_inv = opts->precision == 2;
-  auto bapply = [&](int64_t rstride, const T* r, const int* act) {
-    if constexpr (std::is_same<T, float2>::value) {
-      if (half_inv) {
-        launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, o->minv16, nrhs, rstride, r, ld, zT, act, s);
-        return;
+  auto bapply = [&](int64_t rstride, const auto* r, const int* act) {
+    using RT = std::remove_cv_t<std::remove_pointer_t<decltype(r)>>;
+    if constexpr (std::is_same<RT, hbasis>::value) {
+      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, o->minv16, nrhs, rstride, r, ld, zT, act, s);
+    } else {
+      if constexpr (std::is_same<T, float2>::value) {
+        if (half_inv) {
+          launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, o->minv16, nrhs, rstride, r, ld, zT, act, s);
+          return;
+        }
       }
+      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, rstride, r, ld, zT, act, s);
     }
-    launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, rstride, r, ld, zT, act, s);
   };
   std::vector<int> done(nrhs, 0), run(nrhs), cyc(nrhs), kc(nrhs);
   std::vector<double> beta(bnorm), est((size_t)nrhs * (m + 1));
@@ -1148,19 +1169,20 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     HIP_TRY(hipMemcpyAsync(B.cyc, cyc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(B.run, run.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(B.beta, beta.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-    // pending v0 = r / beta (stored in T); the delayed-CGS2 step j finishes v_j
-    launch_to_storage_b(n, rvec, ld, V, vstride, nrhs, s);
-    launch_scale_by_inv_b(n, (const T*)V, vstride, B.beta, V, vstride, B.cyc, nrhs, s);
+    // pending v0 = r / beta, written straight into basis storage; the
+    // delayed-CGS2 step j finishes v_j
+    launch_scale_by_inv_b(n, rvec, ld, B.beta, V, vstride, B.cyc, nrhs, s);
     int jstart = 0;      // first estimate index not yet checked (common to the running systems)
     for (int j = 0; j < m; ++j) {
-      T* vj = V + (int64_t)j * ld;
-      bapply(vstride, (const T*)vj, B.run);
+      VT* vj = V + (int64_t)j * ld;
+      bapply(vstride, (const VT*)vj, B.run);
       launch_spmv_b(n, o->rowptr, o->col, val, nrhs, ld, (const T*)zT, (const T*)nullptr, wT, B.run, s);
-      launch_mdot2_b(n, (const T*)V, ld, vstride, j, (const T*)vj, (const T*)wT, ld, B.part, pstride, B.run, nrhs, s);
+      launch_mdot2_b(n, (const VT*)V, ld, vstride, j, (const VT*)vj, (const T*)wT, ld, B.part, pstride, B.run, nrhs,
+                     s);
       launch_reduce_cols_b(2 * j + 2, nparts2, B.part, pstride, B.dots, dstride, nullptr, B.run, nrhs, s);
       launch_dcgs_coef_b(j, m, B.dots, dstride, B.Hraw, B.tnorm, B.coef, B.Hd, B.csd, B.snd, B.gd, B.beta, B.bnorm,
                          B.est, B.run, nrhs, s);
-      launch_dcgs_update_b(n, (const T*)V, ld, vstride, j, B.coef, dstride, vj, wT, ld, B.rpart, B.tnorm, B.run,
+      launch_dcgs_update_b(n, (const VT*)V, ld, vstride, j, B.coef, dstride, vj, wT, ld, B.rpart, B.tnorm, B.run,
                            nrhs, s);
       launch_scale_by_inv_b(n, (const T*)wT, ld, B.tnorm, V + (int64_t)(j + 1) * ld, vstride, B.run, nrhs, s);
       for (int r = 0; r < nrhs; ++r) its[r] += run[r];
@@ -1214,7 +1236,7 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     }
     HIP_TRY(hipMemcpyAsync(B.kcols, kc.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     launch_backsolve_b(B.kcols, m, B.Hd, B.gd, B.yd, hs, B.cyc, nrhs, s);
-    launch_combine_b(n, (const T*)V, ld, vstride, B.kcols, B.yd, hs, wT, ld, B.cyc, nrhs, s);
+    launch_combine_b(n, (const VT*)V, ld, vstride, B.kcols, B.yd, hs, wT, ld, B.cyc, nrhs, s);
     bapply(ld, (const T*)wT, B.cyc);
     launch_axpy_b(n, (const T*)zT, ld, B.xt, ld, B.cyc, nrhs, s);
     // FP64 true residuals of the penalty-free operator
@@ -1293,8 +1315,9 @@ eddy_status eddy_solve_batched(eddy_op* o, int32_t nrhs, const eddy_c128* b_dev,
   launch_norm2_b(n, (const double2*)B.bt, ld, B.rpart, B.nrm, nullptr, nrhs, s);
   HIP_TRY(hipMemcpyAsync(bnorm.data(), B.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (opts->precision >= 1) st = run_batched<float2>(o, B, opts, bnorm, its, R, s);
-  else st = run_batched<double2>(o, B, opts, bnorm, its, R, s);
+  if (opts->precision == 2) st = run_batched<float2, hbasis>(o, B, opts, bnorm, its, R, s);
+  else if (opts->precision == 1) st = run_batched<float2, float2>(o, B, opts, bnorm, its, R, s);
+  else st = run_batched<double2, double2>(o, B, opts, bnorm, its, R, s);
   if (st != EDDY_OK) return st;
   bool all = true;
   for (int r = 0; r < nrhs; ++r) {

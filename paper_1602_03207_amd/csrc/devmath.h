@@ -86,6 +86,13 @@ __device__ __forceinline__ double2 ld2(float2 a) { return make_double2(a.x, a.y)
 template <class T> __device__ __forceinline__ T st2(double2 a);
 template <> __device__ __forceinline__ double2 st2<double2>(double2 a) { return a; }
 template <> __device__ __forceinline__ float2 st2<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+__device__ __forceinline__ double2 ld2(hbasis a) {
+  const float2 f = unpack_h2(a.b);
+  return make_double2((double)f.x * (1.0 / 16384.0), (double)f.y * (1.0 / 16384.0));
+}
+template <> __device__ __forceinline__ hbasis st2<hbasis>(double2 a) {
+  return hbasis{pack_h2(a.x * 16384.0, a.y * 16384.0)};
+}
 template <class T> __device__ __forceinline__ T zero2();
 template <> __device__ __forceinline__ double2 zero2<double2>() { return make_double2(0.0, 0.0); }
 template <> __device__ __forceinline__ float2 zero2<float2>() { return make_float2(0.f, 0.f); }

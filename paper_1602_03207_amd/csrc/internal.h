@@ -57,6 +57,14 @@ constexpr int kGnnScratch = 7 * kGnnP * kGnnWidth + kGnnP * kGnnFout +
 constexpr int kSellC = 64;
 constexpr int kSellWindow = 1024;
 
+// Krylov basis entry in complex half precision (real part in the low 16
+// bits), stored scaled by 2^14: the basis vectors have unit norm, so every
+// entry is at most 1 in magnitude and the scaled parts stay inside
+// binary16's normal range down to ~4e-9.
+struct hbasis {
+  uint32_t b;
+};
+
 inline int pair6(int l, int m) {    // upper-triangle slot of a symmetric 6x6
   if (l > m) { int t = l; l = m; m = t; }
   return l * 6 - (l * (l - 1)) / 2 + (m - l);

@@ -51,9 +51,10 @@ void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, 
 int spmv_full_grid(int64_t ns);
 void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2* sval, float2* sval32,
                         hipStream_t st);
-// MT: storage of the inverses, T or (with T = float2) packed complex half (uint32_t)
-template <class T, class MT>
-void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const T* r, T* z,
+// MT: storage of the inverses, T or (with T = float2) packed complex half
+// (uint32_t); RT: storage of r (T, or hbasis with T = float2)
+template <class T, class MT, class RT>
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const RT* r, T* z,
                         hipStream_t st);
 // complex128 -> packed complex half (round to nearest even)
 void launch_to_c16(int64_t n, const double2* in, uint32_t* out, hipStream_t st);
@@ -69,20 +70,20 @@ void launch_reduce_cols(int q, int nparts, const double2* partial, double2* out,
                         const int* flag = nullptr);
 template <class T>
 void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipStream_t st);
-template <class T>
-void launch_scale_by_inv(int64_t n, const T* w, const double* norm, T* v, hipStream_t st);
+template <class Ti, class To>
+void launch_scale_by_inv(int64_t n, const Ti* w, const double* norm, To* v, hipStream_t st);
 template <class Ti, class To>
 void launch_scale_host(int64_t n, const Ti* w, double a, To* v, hipStream_t st);
-template <class T>
-void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y, T* u, hipStream_t st);
+template <class VT, class T>
+void launch_combine(int64_t n, const VT* V, int64_t ldv, int q, const double2* y, T* u, hipStream_t st);
 template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st);
 void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
 // ---- batched systems (vectors of system r at offset r * stride; grid.z = r;
 // `active` (device int[nrhs], may be null) masks systems out)
-template <class T, class MT>
+template <class T, class MT, class RT>
 void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, int nrhs,
-                          int64_t rstride, const T* r, int64_t zstride, T* z, const int* active, hipStream_t st);
+                          int64_t rstride, const RT* r, int64_t zstride, T* z, const int* active, hipStream_t st);
 template <class T>
 void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, int nrhs, int64_t ld, const T* x,
                    const T* b, T* y, const int* active, hipStream_t st);
@@ -91,16 +92,16 @@ void launch_reduce_cols_b(int q, int nparts, const double2* partial, int64_t pst
 template <class T>
 void launch_norm2_b(int64_t n, const T* w, int64_t wstride, double* partial, double* out_norm, const int* active,
                     int nrhs, hipStream_t st);
-template <class T>
-void launch_scale_by_inv_b(int64_t n, const T* w, int64_t wstride, const double* norm, T* v, int64_t vstride,
+template <class Ti, class To>
+void launch_scale_by_inv_b(int64_t n, const Ti* w, int64_t wstride, const double* norm, To* v, int64_t vstride,
                            const int* active, int nrhs, hipStream_t st);
 void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, int64_t h2stride,
                      const double* nrm, double2* H, double* cs, double2* sn, double2* g, const double* beta,
                      const double* bnorm, double* est, const int* active, int nrhs, hipStream_t st);
 void launch_backsolve_b(const int* ks, int m, const double2* H, const double2* g, double2* y, int64_t ystride,
                         const int* active, int nrhs, hipStream_t st);
-template <class T>
-void launch_combine_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, const int* qs, const double2* y,
+template <class VT, class T>
+void launch_combine_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, const int* qs, const double2* y,
                       int64_t ystride, T* u, int64_t ustride, const int* active, int nrhs, hipStream_t st);
 template <class T>
 void launch_axpy_b(int64_t n, const T* z, int64_t zstride, double2* x, int64_t xstride, const int* active, int nrhs,
@@ -115,8 +116,9 @@ void launch_to_storage_b(int64_t n, const double2* in, int64_t istride, T* out, 
 // the step's small linear algebra + lagged Givens rotation, and the fused
 // update (finished basis vector into v, next direction into w, ||w||).
 int mdot2_parts(int64_t n);
-template <class T>
-void launch_mdot2(int64_t n, const T* V, int64_t ldv, int q, const T* v, const T* w, double2* partial,
+// VT: storage of the basis V and the pending vector v (T, or hbasis with T = float2)
+template <class VT, class T>
+void launch_mdot2(int64_t n, const VT* V, int64_t ldv, int q, const VT* v, const T* w, double2* partial,
                   hipStream_t st);
 // Sall [m x m] / rhoall [m] (may be null) record each step's finishing
 // transform (s, rho) for flexible cycles; launch_flex_coeffs then maps the
@@ -129,18 +131,18 @@ void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall,
 // batched forms (system z: V at z * vstride, w at z * wstride, partial at
 // z * pstride, dots and coef at z * dstride, Hessenberg data at the strides
 // of launch_givens_b; beta, bnorm, tnorm per system; active masks systems)
-template <class T>
-void launch_mdot2_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* v, const T* w,
+template <class VT, class T>
+void launch_mdot2_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const VT* v, const T* w,
                     int64_t wstride, double2* partial, int64_t pstride, const int* active, int nrhs, hipStream_t st);
 void launch_dcgs_coef_b(int j, int m, const double2* dots, int64_t dstride, double2* Hraw, const double* tnorm,
                         double2* coef, double2* H, double* cs, double2* sn, double2* g, const double* beta,
                         const double* bnorm, double* est, const int* active, int nrhs, hipStream_t st);
-template <class T>
-void launch_dcgs_update_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
-                          int64_t cstride, T* v, T* w, int64_t wstride, double* rpart, double* out_norm,
+template <class VT, class T>
+void launch_dcgs_update_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
+                          int64_t cstride, VT* v, T* w, int64_t wstride, double* rpart, double* out_norm,
                           const int* active, int nrhs, hipStream_t st);
-template <class T>
-void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,
+template <class VT, class T>
+void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double2* coef, VT* v, T* w, double* rpart,
                         double* out_norm, hipStream_t st);
 // Hessenberg least squares on the device
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,

@@ -655,10 +655,10 @@ __global__ __launch_bounds__(kThreads) void k_sell_gather(int64_t tot, const int
 
 // z_I = Minv_I r_I, one 64-lane wavefront per block, 4 blocks per workgroup;
 // MT the storage of the inverses (T, or packed complex half with T = float2).
-template <class T, class MT>
+template <class T, class MT, class RT>
 __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int* __restrict__ blk_ptr,
                                                           const int* __restrict__ blk_dofs,
-                                                          const MT* __restrict__ minv, const T* __restrict__ r,
+                                                          const MT* __restrict__ minv, const RT* __restrict__ r,
                                                           T* __restrict__ z) {
   __shared__ T rl[4][kMaxBlock];
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(int64_t nb, const int*
     sz = blk_ptr[k + 1] - b0;
     if (i < sz) dof = blk_dofs[b0 + i];
   }
-  rl[w][i] = dof >= 0 ? r[dof] : zero2<T>();
+  rl[w][i] = dof >= 0 ? st2<T>(ld2(r[dof])) : zero2<T>();
   __syncthreads();
   if (dof < 0) return;
   const MT* Mk = minv + k * kMaxBlock * kMaxBlock;
@@ -751,9 +751,9 @@ __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restric
 // v^H v and v^H w.
 constexpr int kDot2Rows = 2 * kThreads;
 constexpr int kDot2MaxBlocks = 1024;
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                    const T* __restrict__ v, const T* __restrict__ w,
+template <class VT, class T>
+__global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const VT* __restrict__ V, int64_t ldv, int q,
+                                                    const VT* __restrict__ v, const T* __restrict__ w,
                                                     double2* __restrict__ partial, int64_t vstride, int64_t wstride,
                                                     int64_t pstride, const int* __restrict__ active) {
   // system z of a batch (grid.z); strides are 0 for a single system
@@ -788,7 +788,7 @@ __global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const T* __restri
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if (k < cnt) {
-        const T* Vk = V + (int64_t)(c0 + k) * ldv;
+        const VT* Vk = V + (int64_t)(c0 + k) * ldv;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int64_t i = base + (int64_t)r * kThreads;
@@ -893,9 +893,9 @@ __global__ __launch_bounds__(kThreads) void k_norm2_final(const double* __restri
   if (threadIdx.x == 0) out[0] = sqrt(acc);
 }
 
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const T* __restrict__ w,
-                                                           const double* __restrict__ nrm, T* __restrict__ v,
+template <class Ti, class To>
+__global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const Ti* __restrict__ w,
+                                                           const double* __restrict__ nrm, To* __restrict__ v,
                                                            int64_t wstride, int64_t vstride,
                                                            const int* __restrict__ active) {
   const int z = blockIdx.z;
@@ -908,7 +908,7 @@ __global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const T* _
   const double a = nrm[0];
   const double f = a > 0.0 ? 1.0 / a : 0.0;
   const double2 x = ld2(w[i]);
-  v[i] = st2<T>(make_double2(x.x * f, x.y * f));
+  v[i] = st2<To>(make_double2(x.x * f, x.y * f));
 }
 
 template <class Ti, class To>
@@ -920,8 +920,8 @@ __global__ __launch_bounds__(kThreads) void k_scale_host(int64_t n, const Ti* __
   v[i] = st2<To>(make_double2(x.x * a, x.y * a));
 }
 
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_combine(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
+template <class VT, class T>
+__global__ __launch_bounds__(kThreads) void k_combine(int64_t n, const VT* __restrict__ V, int64_t ldv, int q,
                                                       const double2* __restrict__ y, T* __restrict__ u,
                                                       int64_t vstride, int64_t ystride, int64_t ustride,
                                                       const int* __restrict__ qs, const int* __restrict__ active) {
@@ -1164,9 +1164,9 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* _
 // DCGS2 update, one read of V: v <- (v - V s) / rho (the finished basis
 // vector j, in place) and w <- w / rho - (kappa / rho) v - V g (the next
 // direction, in place), with rpart the per-block sums of |w|^2.
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_dcgs_update(int64_t n, const T* __restrict__ V, int64_t ldv, int q,
-                                                          const double2* __restrict__ coef, T* __restrict__ v,
+template <class VT, class T>
+__global__ __launch_bounds__(kThreads) void k_dcgs_update(int64_t n, const VT* __restrict__ V, int64_t ldv, int q,
+                                                          const double2* __restrict__ coef, VT* __restrict__ v,
                                                           T* __restrict__ w, double* __restrict__ rpart,
                                                           int64_t vstride, int64_t wstride, int64_t cstride,
                                                           const int* __restrict__ active) {
@@ -1195,7 +1195,7 @@ __global__ __launch_bounds__(kThreads) void k_dcgs_update(int64_t n, const T* __
       qa = cfma(x, cs_[k], qa);
       ga = cfma(x, cg_[k], ga);
     }
-    v[i] = st2<T>(make_double2((vi.x - qa.x) * ir, (vi.y - qa.y) * ir));
+    v[i] = st2<VT>(make_double2((vi.x - qa.x) * ir, (vi.y - qa.y) * ir));
     const double2 bvi = cmul(bv, vi);
     const T ws = st2<T>(make_double2(wi.x * ir + bvi.x - ga.x, wi.y * ir + bvi.y - ga.y));
     w[i] = ws;
@@ -1250,11 +1250,11 @@ __global__ void k_backsolve_b(const int* __restrict__ ks, int m, const double2* 
 // per launch for up to kBatchChunk systems (vectors of system r at r * ld).
 
 // z_r = Minv r_r for the active systems, one wavefront per block.
-template <class T, class MT>
+template <class T, class MT, class RT>
 __global__ __launch_bounds__(kThreads) void k_block_apply_b(int64_t nb, const int* __restrict__ blk_ptr,
                                                             const int* __restrict__ blk_dofs,
                                                             const MT* __restrict__ minv, int nrhs, int64_t rstride,
-                                                            const T* __restrict__ r, int64_t zstride,
+                                                            const RT* __restrict__ r, int64_t zstride,
                                                             T* __restrict__ z, const int* __restrict__ active) {
   __shared__ T rl[4][kBatchChunk][kMaxBlock];
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
@@ -1271,7 +1271,7 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_b(int64_t nb, const in
 #pragma unroll
     for (int q = 0; q < kBatchChunk; ++q) {
       const bool on = q < cn && dof >= 0 && (!active || active[c0 + q]);
-      rl[w][q][i] = on ? r[(int64_t)(c0 + q) * rstride + dof] : zero2<T>();
+      rl[w][q][i] = on ? st2<T>(ld2(r[(int64_t)(c0 + q) * rstride + dof])) : zero2<T>();
     }
     __syncthreads();
     if (dof >= 0) {
@@ -1622,10 +1622,10 @@ void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2
                         hipStream_t st) {
   k_sell_gather<<<blocks_for(tot), kThreads, 0, st>>>(tot, src, val, sval, sval32);
 }
-template <class T, class MT>
-void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const T* r, T* z,
+template <class T, class MT, class RT>
+void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const RT* r, T* z,
                         hipStream_t st) {
-  k_block_apply<T, MT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
+  k_block_apply<T, MT, RT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
 }
 int mdot2_parts(int64_t n) {
   const int64_t tiles = (n + kDot2Rows - 1) / kDot2Rows;
@@ -1646,27 +1646,27 @@ void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipS
   k_norm2_partial<T><<<kRedBlocks, kThreads, 0, st>>>(n, w, partial, 0, nullptr);
   k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm, nullptr, nullptr);
 }
-template <class T>
-void launch_scale_by_inv(int64_t n, const T* w, const double* norm, T* v, hipStream_t st) {
-  k_scale_by_inv<T><<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v, 0, 0, nullptr);
+template <class Ti, class To>
+void launch_scale_by_inv(int64_t n, const Ti* w, const double* norm, To* v, hipStream_t st) {
+  k_scale_by_inv<Ti, To><<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v, 0, 0, nullptr);
 }
 template <class Ti, class To>
 void launch_scale_host(int64_t n, const Ti* w, double a, To* v, hipStream_t st) {
   k_scale_host<Ti, To><<<blocks_for(n), kThreads, 0, st>>>(n, w, a, v);
 }
-template <class T>
-void launch_combine(int64_t n, const T* V, int64_t ldv, int q, const double2* y, T* u, hipStream_t st) {
-  k_combine<T><<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, y, u, 0, 0, 0, nullptr, nullptr);
+template <class VT, class T>
+void launch_combine(int64_t n, const VT* V, int64_t ldv, int q, const double2* y, T* u, hipStream_t st) {
+  k_combine<VT, T><<<blocks_for(n), kThreads, 0, st>>>(n, V, ldv, q, y, u, 0, 0, 0, nullptr, nullptr);
 }
 template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
   k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x, 0, 0, nullptr);
 }
-template <class T>
-void launch_mdot2(int64_t n, const T* V, int64_t ldv, int q, const T* v, const T* w, double2* partial,
+template <class VT, class T>
+void launch_mdot2(int64_t n, const VT* V, int64_t ldv, int q, const VT* v, const T* w, double2* partial,
                   hipStream_t st) {
   dim3 grid(mdot2_parts(n), q > 0 ? (q + 7) / 8 : 1);
-  k_mdot2<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, 0, 0, 0, nullptr);
+  k_mdot2<VT, T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, 0, 0, 0, nullptr);
 }
 void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
                       double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
@@ -1691,17 +1691,17 @@ __global__ void k_flex_coeffs(int k, int m, const double2* __restrict__ Sall, co
 void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall, double2* y, hipStream_t st) {
   k_flex_coeffs<<<1, 64, 0, st>>>(k, m, Sall, rhoall, y);
 }
-template <class T>
-void launch_dcgs_update(int64_t n, const T* V, int64_t ldv, int q, const double2* coef, T* v, T* w, double* rpart,
+template <class VT, class T>
+void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double2* coef, VT* v, T* w, double* rpart,
                         double* out_norm, hipStream_t st) {
-  k_dcgs_update<T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, 0, 0, 0, nullptr);
+  k_dcgs_update<VT, T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, 0, 0, 0, nullptr);
   k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, nullptr, nullptr);
 }
-template <class T>
-void launch_mdot2_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const T* v, const T* w,
+template <class VT, class T>
+void launch_mdot2_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const VT* v, const T* w,
                     int64_t wstride, double2* partial, int64_t pstride, const int* active, int nrhs, hipStream_t st) {
   dim3 grid(mdot2_parts(n), q > 0 ? (q + 7) / 8 : 1, nrhs);
-  k_mdot2<T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, vstride, wstride, pstride, active);
+  k_mdot2<VT, T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, vstride, wstride, pstride, active);
 }
 void launch_dcgs_coef_b(int j, int m, const double2* dots, int64_t dstride, double2* Hraw, const double* tnorm,
                         double2* coef, double2* H, double* cs, double2* sn, double2* g, const double* beta,
@@ -1709,11 +1709,11 @@ void launch_dcgs_coef_b(int j, int m, const double2* dots, int64_t dstride, doub
   k_dcgs_coef<<<dim3(1, 1, nrhs), 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, 0.0, 1.0, est, nullptr,
                                                nullptr, beta, bnorm, dstride, active);
 }
-template <class T>
-void launch_dcgs_update_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
-                          int64_t cstride, T* v, T* w, int64_t wstride, double* rpart, double* out_norm,
+template <class VT, class T>
+void launch_dcgs_update_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
+                          int64_t cstride, VT* v, T* w, int64_t wstride, double* rpart, double* out_norm,
                           const int* active, int nrhs, hipStream_t st) {
-  k_dcgs_update<T><<<dim3(kRedBlocks, 1, nrhs), kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, vstride, wstride,
+  k_dcgs_update<VT, T><<<dim3(kRedBlocks, 1, nrhs), kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, vstride, wstride,
                                                                   cstride, active);
   k_norm2_final<<<dim3(1, 1, nrhs), kThreads, 0, st>>>(rpart, out_norm, nullptr, active);
 }
@@ -1725,10 +1725,10 @@ void launch_backsolve(int k, int m, const double2* H, const double2* g, double2*
   k_backsolve<<<1, 64, 0, st>>>(k, m, H, g, y);
 }
 // ---- batched launch wrappers (grid.z = system index)
-template <class T, class MT>
+template <class T, class MT, class RT>
 void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, int nrhs,
-                          int64_t rstride, const T* r, int64_t zstride, T* z, const int* active, hipStream_t st) {
-  k_block_apply_b<T, MT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, nrhs, rstride, r, zstride,
+                          int64_t rstride, const RT* r, int64_t zstride, T* z, const int* active, hipStream_t st) {
+  k_block_apply_b<T, MT, RT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, nrhs, rstride, r, zstride,
                                                               z, active);
 }
 template <class T>
@@ -1749,11 +1749,11 @@ void launch_norm2_b(int64_t n, const T* w, int64_t wstride, double* partial, dou
   dim3 g1(1, 1, nrhs);
   k_norm2_final<<<g1, kThreads, 0, st>>>(partial, out_norm, nullptr, active);
 }
-template <class T>
-void launch_scale_by_inv_b(int64_t n, const T* w, int64_t wstride, const double* norm, T* v, int64_t vstride,
+template <class Ti, class To>
+void launch_scale_by_inv_b(int64_t n, const Ti* w, int64_t wstride, const double* norm, To* v, int64_t vstride,
                            const int* active, int nrhs, hipStream_t st) {
   dim3 grid(blocks_for(n), 1, nrhs);
-  k_scale_by_inv<T><<<grid, kThreads, 0, st>>>(n, w, norm, v, wstride, vstride, active);
+  k_scale_by_inv<Ti, To><<<grid, kThreads, 0, st>>>(n, w, norm, v, wstride, vstride, active);
 }
 void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, int64_t h2stride,
                      const double* nrm, double2* H, double* cs, double2* sn, double2* g, const double* beta,
@@ -1766,11 +1766,11 @@ void launch_backsolve_b(const int* ks, int m, const double2* H, const double2* g
   dim3 grid(1, 1, nrhs);
   k_backsolve_b<<<grid, 64, 0, st>>>(ks, m, H, g, y, ystride, active);
 }
-template <class T>
-void launch_combine_b(int64_t n, const T* V, int64_t ldv, int64_t vstride, const int* qs, const double2* y,
+template <class VT, class T>
+void launch_combine_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, const int* qs, const double2* y,
                       int64_t ystride, T* u, int64_t ustride, const int* active, int nrhs, hipStream_t st) {
   dim3 grid(blocks_for(n), 1, nrhs);
-  k_combine<T><<<grid, kThreads, 0, st>>>(n, V, ldv, 0, y, u, vstride, ystride, ustride, qs, active);
+  k_combine<VT, T><<<grid, kThreads, 0, st>>>(n, V, ldv, 0, y, u, vstride, ystride, ustride, qs, active);
 }
 template <class T>
 void launch_axpy_b(int64_t n, const T* z, int64_t zstride, double2* x, int64_t xstride, const int* active, int nrhs,
@@ -1796,53 +1796,80 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
   template void launch_spmv<T>(int64_t, const int*, const int*, const int*, const T*, int64_t, const int*,       \
                                const int*, const double*, const double2*, const T*, const double2*, T*,          \
                                hipStream_t, int, int, const int*);                                               \
-  template void launch_block_apply<T, T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t);   \
+  template void launch_block_apply<T, T, T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t); \
   template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t, int, const int*); \
   template void launch_norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                \
-  template void launch_scale_by_inv<T>(int64_t, const T*, const double*, T*, hipStream_t);                        \
+  template void launch_scale_by_inv<T, T>(int64_t, const T*, const double*, T*, hipStream_t);                     \
   template void launch_scale_host<double2, T>(int64_t, const double2*, double, T*, hipStream_t);                  \
-  template void launch_combine<T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);              \
+  template void launch_combine<T, T>(int64_t, const T*, int64_t, int, const double2*, T*, hipStream_t);           \
   template void launch_axpy<T>(int64_t, const T*, double2*, hipStream_t);
 EDDY_INST(double2)
 EDDY_INST(float2)
 #undef EDDY_INST
-template void launch_mdot2<double2>(int64_t, const double2*, int64_t, int, const double2*, const double2*, double2*,
-                                    hipStream_t);
-template void launch_mdot2<float2>(int64_t, const float2*, int64_t, int, const float2*, const float2*, double2*,
-                                   hipStream_t);
-template void launch_dcgs_update<double2>(int64_t, const double2*, int64_t, int, const double2*, double2*, double2*,
-                                          double*, double*, hipStream_t);
-template void launch_dcgs_update<float2>(int64_t, const float2*, int64_t, int, const double2*, float2*, float2*,
-                                         double*, double*, hipStream_t);
-template void launch_mdot2_b<double2>(int64_t, const double2*, int64_t, int64_t, int, const double2*, const double2*,
+template void launch_mdot2<double2, double2>(int64_t, const double2*, int64_t, int, const double2*, const double2*,
+                                             double2*, hipStream_t);
+template void launch_mdot2<float2, float2>(int64_t, const float2*, int64_t, int, const float2*, const float2*,
+                                           double2*, hipStream_t);
+template void launch_mdot2<hbasis, float2>(int64_t, const hbasis*, int64_t, int, const hbasis*, const float2*,
+                                           double2*, hipStream_t);
+template void launch_dcgs_update<double2, double2>(int64_t, const double2*, int64_t, int, const double2*, double2*,
+                                                   double2*, double*, double*, hipStream_t);
+template void launch_dcgs_update<float2, float2>(int64_t, const float2*, int64_t, int, const double2*, float2*,
+                                                 float2*, double*, double*, hipStream_t);
+template void launch_dcgs_update<hbasis, float2>(int64_t, const hbasis*, int64_t, int, const double2*, hbasis*,
+                                                 float2*, double*, double*, hipStream_t);
+template void launch_scale_by_inv<float2, hbasis>(int64_t, const float2*, const double*, hbasis*, hipStream_t);
+template void launch_scale_host<double2, hbasis>(int64_t, const double2*, double, hbasis*, hipStream_t);
+template void launch_combine<hbasis, float2>(int64_t, const hbasis*, int64_t, int, const double2*, float2*,
+                                             hipStream_t);
+template void launch_block_apply<float2, uint32_t, hbasis>(int64_t, const int*, const int*, const uint32_t*,
+                                                           const hbasis*, float2*, hipStream_t);
+template void launch_mdot2_b<double2, double2>(int64_t, const double2*, int64_t, int64_t, int, const double2*, const double2*,
                                       int64_t, double2*, int64_t, const int*, int, hipStream_t);
-template void launch_mdot2_b<float2>(int64_t, const float2*, int64_t, int64_t, int, const float2*, const float2*,
+template void launch_mdot2_b<float2, float2>(int64_t, const float2*, int64_t, int64_t, int, const float2*, const float2*,
                                      int64_t, double2*, int64_t, const int*, int, hipStream_t);
-template void launch_dcgs_update_b<double2>(int64_t, const double2*, int64_t, int64_t, int, const double2*, int64_t,
+template void launch_dcgs_update_b<double2, double2>(int64_t, const double2*, int64_t, int64_t, int, const double2*, int64_t,
                                             double2*, double2*, int64_t, double*, double*, const int*, int,
                                             hipStream_t);
-template void launch_dcgs_update_b<float2>(int64_t, const float2*, int64_t, int64_t, int, const double2*, int64_t,
+template void launch_dcgs_update_b<float2, float2>(int64_t, const float2*, int64_t, int64_t, int, const double2*, int64_t,
                                            float2*, float2*, int64_t, double*, double*, const int*, int,
                                            hipStream_t);
 #define EDDY_INST_B(T)                                                                                            \
-  template void launch_block_apply_b<T, T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*,     \
-                                           int64_t, T*, const int*, hipStream_t);                                 \
+  template void launch_block_apply_b<T, T, T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*,  \
+                                              int64_t, T*, const int*, hipStream_t);                              \
   template void launch_spmv_b<T>(int64_t, const int*, const int*, const T*, int, int64_t, const T*, const T*, T*,  \
                                  const int*, hipStream_t);                                                        \
   template void launch_norm2_b<T>(int64_t, const T*, int64_t, double*, double*, const int*, int, hipStream_t);      \
-  template void launch_scale_by_inv_b<T>(int64_t, const T*, int64_t, const double*, T*, int64_t, const int*, int, \
-                                         hipStream_t);                                                            \
-  template void launch_combine_b<T>(int64_t, const T*, int64_t, int64_t, const int*, const double2*, int64_t, T*,  \
-                                    int64_t, const int*, int, hipStream_t);                                       \
+  template void launch_scale_by_inv_b<T, T>(int64_t, const T*, int64_t, const double*, T*, int64_t, const int*,  \
+                                            int, hipStream_t);                                                    \
+  template void launch_combine_b<T, T>(int64_t, const T*, int64_t, int64_t, const int*, const double2*, int64_t,  \
+                                       T*, int64_t, const int*, int, hipStream_t);                                \
   template void launch_axpy_b<T>(int64_t, const T*, int64_t, double2*, int64_t, const int*, int, hipStream_t);      \
   template void launch_to_storage_b<T>(int64_t, const double2*, int64_t, T*, int64_t, int, hipStream_t);
 EDDY_INST_B(double2)
 EDDY_INST_B(float2)
 #undef EDDY_INST_B
-template void launch_block_apply<float2, uint32_t>(int64_t, const int*, const int*, const uint32_t*, const float2*,
-                                                   float2*, hipStream_t);
-template void launch_block_apply_b<float2, uint32_t>(int64_t, const int*, const int*, const uint32_t*, int, int64_t,
-                                                     const float2*, int64_t, float2*, const int*, hipStream_t);
+template void launch_block_apply<float2, uint32_t, float2>(int64_t, const int*, const int*, const uint32_t*,
+                                                           const float2*, float2*, hipStream_t);
+template void launch_block_apply_b<float2, uint32_t, float2>(int64_t, const int*, const int*, const uint32_t*, int,
+                                                             int64_t, const float2*, int64_t, float2*, const int*,
+                                                             hipStream_t);
+template void launch_block_apply_b<float2, uint32_t, hbasis>(int64_t, const int*, const int*, const uint32_t*, int,
+                                                             int64_t, const hbasis*, int64_t, float2*, const int*,
+                                                             hipStream_t);
+template void launch_scale_by_inv_b<double2, float2>(int64_t, const double2*, int64_t, const double*, float2*, int64_t,
+                                                     const int*, int, hipStream_t);
+template void launch_scale_by_inv_b<double2, hbasis>(int64_t, const double2*, int64_t, const double*, hbasis*, int64_t,
+                                                     const int*, int, hipStream_t);
+template void launch_scale_by_inv_b<float2, hbasis>(int64_t, const float2*, int64_t, const double*, hbasis*, int64_t,
+                                                    const int*, int, hipStream_t);
+template void launch_combine_b<hbasis, float2>(int64_t, const hbasis*, int64_t, int64_t, const int*, const double2*,
+                                               int64_t, float2*, int64_t, const int*, int, hipStream_t);
+template void launch_mdot2_b<hbasis, float2>(int64_t, const hbasis*, int64_t, int64_t, int, const hbasis*,
+                                             const float2*, int64_t, double2*, int64_t, const int*, int, hipStream_t);
+template void launch_dcgs_update_b<hbasis, float2>(int64_t, const hbasis*, int64_t, int64_t, int, const double2*,
+                                                   int64_t, hbasis*, float2*, int64_t, double*, double*, const int*,
+                                                   int, hipStream_t);
 __global__ __launch_bounds__(kThreads) void k_to_c16(int64_t n, const double2* __restrict__ in,
                                                      uint32_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

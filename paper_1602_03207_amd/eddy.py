@@ -307,7 +307,7 @@ class Operator:
 
     def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64", gnn_theta=None):
         """precision: "fp64", "mixed" (complex64 Krylov process, FP64 outer residual), or
-        "mixed16" (as mixed, with complex-half block-Jacobi inverses).
+        "mixed16" (as mixed, with the block-Jacobi inverses and the Krylov basis in complex half).
         gnn_theta: float32 device tensor of EDDY_GNN_PARAMS network parameters
         (the learned coarse correction with fallback), or None."""
         if gnn_theta is not None:
