@@ -103,3 +103,85 @@ template <class T> __device__ __forceinline__ T cfmaT(T a, T b, T acc) {
   return acc;
 }
 
+
+// ---- row groups: rows_of<T>::R consecutive entries of one vector moved
+// with 16-byte accesses (the first entry 16-byte aligned).  Complex-half
+// entries come back as stored, i.e. times 2^14; basis_unscale<T>() is the
+// factor that undoes it (1 for the other types), applied by the caller
+// once per sum instead of once per entry.
+template <class T> struct rows_of;
+template <> struct rows_of<double2> { static constexpr int R = 2; };
+template <> struct rows_of<float2> { static constexpr int R = 4; };
+template <> struct rows_of<hbasis> { static constexpr int R = 4; };
+template <class T> __device__ __forceinline__ constexpr double basis_unscale() { return 1.0; }
+template <> __device__ __forceinline__ constexpr double basis_unscale<hbasis>() { return 1.0 / 16384.0; }
+__device__ __forceinline__ double2 raw2(double2 a) { return a; }
+__device__ __forceinline__ double2 raw2(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ double2 raw2(hbasis a) {
+  const float2 f = unpack_h2(a.b);
+  return make_double2(f.x, f.y);
+}
+__device__ __forceinline__ void ld_rows(const double2* __restrict__ p, double2* o) {
+  o[0] = p[0];
+  o[1] = p[1];
+}
+__device__ __forceinline__ void ld_rows(const float2* __restrict__ p, double2* o) {
+  const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+  o[0] = make_double2(a.x, a.y);
+  o[1] = make_double2(a.z, a.w);
+  o[2] = make_double2(b.x, b.y);
+  o[3] = make_double2(b.z, b.w);
+}
+__device__ __forceinline__ void ld_rows(const hbasis* __restrict__ p, double2* o) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  o[0] = raw2(hbasis{u.x});
+  o[1] = raw2(hbasis{u.y});
+  o[2] = raw2(hbasis{u.z});
+  o[3] = raw2(hbasis{u.w});
+}
+// stores take true values (complex-half entries are scaled here)
+__device__ __forceinline__ void st_rows(double2* __restrict__ p, const double2* x) {
+  p[0] = x[0];
+  p[1] = x[1];
+}
+__device__ __forceinline__ void st_rows(float2* __restrict__ p, const double2* x) {
+  reinterpret_cast<float4*>(p)[0] = make_float4((float)x[0].x, (float)x[0].y, (float)x[1].x, (float)x[1].y);
+  reinterpret_cast<float4*>(p)[1] = make_float4((float)x[2].x, (float)x[2].y, (float)x[3].x, (float)x[3].y);
+}
+__device__ __forceinline__ void st_rows(hbasis* __restrict__ p, const double2* x) {
+  *reinterpret_cast<uint4*>(p) = make_uint4(st2<hbasis>(x[0]).b, st2<hbasis>(x[1]).b, st2<hbasis>(x[2]).b,
+                                            st2<hbasis>(x[3]).b);
+}
+// the same row groups as complex64 (complex-half and complex64 storage only)
+__device__ __forceinline__ void ld_rows(const float2* __restrict__ p, float2* o) {
+  const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+  o[0] = make_float2(a.x, a.y);
+  o[1] = make_float2(a.z, a.w);
+  o[2] = make_float2(b.x, b.y);
+  o[3] = make_float2(b.z, b.w);
+}
+__device__ __forceinline__ void ld_rows(const hbasis* __restrict__ p, float2* o) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  o[0] = unpack_h2(u.x);
+  o[1] = unpack_h2(u.y);
+  o[2] = unpack_h2(u.z);
+  o[3] = unpack_h2(u.w);
+}
+__device__ __forceinline__ float2 rawf(float2 a) { return a; }
+__device__ __forceinline__ float2 rawf(hbasis a) { return unpack_h2(a.b); }
+__device__ __forceinline__ float2 cfma_conj(float2 a, float2 b, float2 acc) {
+  acc.x = fmaf(a.x, b.x, fmaf(a.y, b.y, acc.x));
+  acc.y = fmaf(a.x, b.y, fmaf(-a.y, b.x, acc.y));
+  return acc;
+}
+// per-thread partial sums of the fused dots: complex64 when the direction is
+// complex64 (a thread sums a few row groups; every wider sum is FP64)
+template <class T> struct dot_acc { using type = double2; };
+template <> struct dot_acc<float2> { using type = float2; };
+__device__ __forceinline__ void to_acc(double2 a, double2& o) { o = a; }
+__device__ __forceinline__ void to_acc(double2 a, float2& o) { o = make_float2((float)a.x, (float)a.y); }
+__device__ __forceinline__ double2 raw_as(double2 a, double2) { return a; }
+__device__ __forceinline__ double2 raw_as(float2 a, double2) { return raw2(a); }
+__device__ __forceinline__ double2 raw_as(hbasis a, double2) { return raw2(a); }
+__device__ __forceinline__ float2 raw_as(float2 a, float2) { return a; }
+__device__ __forceinline__ float2 raw_as(hbasis a, float2) { return rawf(a); }

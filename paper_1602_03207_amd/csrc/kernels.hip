@@ -744,18 +744,24 @@ __global__ __launch_bounds__(kThreads) void k_mdot(int64_t n, const T* __restric
 //
 // Fused dots of the pending vector v and the new direction w against the q
 // finished basis vectors, one read of V: partial columns k < q: V_k^H v,
-// q + k: V_k^H w, 2q: v^H v, 2q + 1: v^H w (FP64 accumulation).  Workgroup
-// (x, y) takes the vectors 8y..8y+7 and the tiles of kDot2Rows rows
-// x, x + gridDim.x, ... (kDot2Rows / 256 rows per thread and tile), so the
-// wavefront reductions happen once per workgroup; slice y = 0 also forms
-// v^H v and v^H w.
-constexpr int kDot2Rows = 2 * kThreads;
+// q + k: V_k^H w, 2q: v^H v, 2q + 1: v^H w (FP64 sums beyond a thread's
+// own rows).  Workgroup (x, y) takes the vectors 8y..8y+7 and the tiles x,
+// x + gridDim.x, ...;
+// a thread takes R = rows_of<VT>::R consecutive rows of a tile with 16-byte
+// loads (vec: every vector 16-byte aligned, ldv a multiple of R; otherwise,
+// and for a ragged last group, entry by entry).  A slice with fewer than 8
+// vectors repeats its first one in the spare slots, so the loads of a row
+// group carry no branches and are all issued before the first product; the
+// spare sums are dropped.  The wavefront reductions happen once per
+// workgroup; slice y = 0 also forms v^H v and v^H w.
 constexpr int kDot2MaxBlocks = 1024;
 template <class VT, class T>
 __global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const VT* __restrict__ V, int64_t ldv, int q,
                                                     const VT* __restrict__ v, const T* __restrict__ w,
                                                     double2* __restrict__ partial, int64_t vstride, int64_t wstride,
-                                                    int64_t pstride, const int* __restrict__ active) {
+                                                    int64_t pstride, const int* __restrict__ active, int vec) {
+  constexpr int R = rows_of<VT>::R;
+  static_assert(rows_of<T>::R == R, "basis and direction row groups differ");
   // system z of a batch (grid.z); strides are 0 for a single system
   const int zs = blockIdx.z;
   if (active && !active[zs]) return;
@@ -763,47 +769,71 @@ __global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const VT* __restr
   v += zs * vstride;
   w += zs * wstride;
   partial += zs * pstride;
-  constexpr int R = kDot2Rows / kThreads;
+  using A = typename dot_acc<T>::type;
   __shared__ double2 red[4][18];
+  const int nparts = gridDim.x, bx = blockIdx.x;
   const int c0 = blockIdx.y * 8;
   const int cnt = max(0, min(8, q - c0));
   const bool norms = blockIdx.y == 0;
-  double2 as[8], ar[8];
+  const double us = basis_unscale<VT>();
+  const VT* Vc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) Vc[k] = V + (int64_t)(c0 + (k < cnt ? k : 0)) * ldv;
+  A as[8], ar[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    as[k] = make_double2(0.0, 0.0);
-    ar[k] = make_double2(0.0, 0.0);
+    to_acc(make_double2(0.0, 0.0), as[k]);
+    to_acc(make_double2(0.0, 0.0), ar[k]);
   }
   double aa = 0.0;
   double2 bb = make_double2(0.0, 0.0);
-  for (int64_t base = (int64_t)blockIdx.x * kDot2Rows + threadIdx.x; base < n;
-       base += (int64_t)gridDim.x * kDot2Rows) {
-    double2 vr[R], wr[R];
+  for (int64_t i0 = ((int64_t)bx * kThreads + threadIdx.x) * R; i0 < n; i0 += (int64_t)nparts * kThreads * R) {
+    A vr[R], wr[R];
+    if (vec && i0 + R <= n) {
+      ld_rows(v + i0, vr);
+      ld_rows(w + i0, wr);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t i = base + (int64_t)r * kThreads;
-      vr[r] = i < n ? ld2(v[i]) : make_double2(0.0, 0.0);
-      wr[r] = i < n ? ld2(w[i]) : make_double2(0.0, 0.0);
-    }
+      for (int r = 0; r < R; ++r) {
+        vr[r].x *= us;
+        vr[r].y *= us;
+      }
+      if (cnt > 0) {
+        A x[8][R];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < cnt) {
-        const VT* Vk = V + (int64_t)(c0 + k) * ldv;
+        for (int k = 0; k < 8; ++k) ld_rows(Vc[k] + i0, x[k]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            as[k] = cfma_conj(x[k][r], vr[r], as[k]);
+            ar[k] = cfma_conj(x[k][r], wr[r], ar[k]);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t i = i0 + r;
+        to_acc(i < n ? ld2(v[i]) : make_double2(0.0, 0.0), vr[r]);
+        to_acc(i < n ? ld2(w[i]) : make_double2(0.0, 0.0), wr[r]);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int64_t i = base + (int64_t)r * kThreads;
-          if (i < n) {
-            const double2 x = ld2(Vk[i]);
+          const int64_t i = i0 + r;
+          if (k < cnt && i < n) {
+            const A x = raw_as(Vc[k][i], A{});
             as[k] = cfma_conj(x, vr[r], as[k]);
             ar[k] = cfma_conj(x, wr[r], ar[k]);
           }
         }
-      }
+    }
     if (norms) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        aa = fma(vr[r].x, vr[r].x, fma(vr[r].y, vr[r].y, aa));
-        bb = cfma_conj(vr[r], wr[r], bb);
+        const double2 a = make_double2(vr[r].x, vr[r].y), b = make_double2(wr[r].x, wr[r].y);
+        aa = fma(a.x, a.x, fma(a.y, a.y, aa));
+        bb = cfma_conj(a, b, bb);
       }
     }
   }
@@ -811,11 +841,11 @@ __global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const VT* __restr
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     if (k < cnt) {
-      const double sr = wave_sum(as[k].x), si = wave_sum(as[k].y);
-      const double rr = wave_sum(ar[k].x), ri = wave_sum(ar[k].y);
+      const double sr = wave_sum((double)as[k].x), si = wave_sum((double)as[k].y);
+      const double rr = wave_sum((double)ar[k].x), ri = wave_sum((double)ar[k].y);
       if (ln == 0) {
-        red[wv][k] = make_double2(sr, si);
-        red[wv][8 + k] = make_double2(rr, ri);
+        red[wv][k] = make_double2(sr * us, si * us);
+        red[wv][8 + k] = make_double2(rr * us, ri * us);
       }
     }
   if (norms) {
@@ -835,7 +865,7 @@ __global__ __launch_bounds__(kThreads) void k_mdot2(int64_t n, const VT* __restr
   if (col >= 0) {
     const double2 r = make_double2((red[0][t].x + red[1][t].x) + (red[2][t].x + red[3][t].x),
                                    (red[0][t].y + red[1][t].y) + (red[2][t].y + red[3][t].y));
-    partial[(int64_t)col * gridDim.x + blockIdx.x] = r;
+    partial[(int64_t)col * nparts + bx] = r;
   }
 }
 
@@ -893,22 +923,43 @@ __global__ __launch_bounds__(kThreads) void k_norm2_final(const double* __restri
   if (threadIdx.x == 0) out[0] = sqrt(acc);
 }
 
+// v = w / nrm, each thread scale_rows<Ti, To>() consecutive rows (16-byte
+// accesses when vec, else entry by entry)
+template <class Ti, class To>
+constexpr int scale_rows() {
+  return rows_of<Ti>::R > rows_of<To>::R ? rows_of<Ti>::R : rows_of<To>::R;
+}
 template <class Ti, class To>
 __global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const Ti* __restrict__ w,
                                                            const double* __restrict__ nrm, To* __restrict__ v,
                                                            int64_t wstride, int64_t vstride,
-                                                           const int* __restrict__ active) {
+                                                           const int* __restrict__ active, int vec) {
+  constexpr int R = scale_rows<Ti, To>();
   const int z = blockIdx.z;
   if (active && !active[z]) return;
   w += z * wstride;
   v += z * vstride;
   nrm += z;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R;
+  if (i0 >= n) return;
   const double a = nrm[0];
   const double f = a > 0.0 ? 1.0 / a : 0.0;
-  const double2 x = ld2(w[i]);
-  v[i] = st2<To>(make_double2(x.x * f, x.y * f));
+  if (vec && i0 + R <= n) {
+    constexpr int Gi = rows_of<Ti>::R, Go = rows_of<To>::R;
+    const double fr = f * basis_unscale<Ti>();
+    double2 x[R];
+#pragma unroll
+    for (int g = 0; g < R; g += Gi) ld_rows(w + i0 + g, x + g);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = make_double2(x[r].x * fr, x[r].y * fr);
+#pragma unroll
+    for (int g = 0; g < R; g += Go) st_rows(v + i0 + g, x + g);
+    return;
+  }
+  for (int r = 0; r < R && i0 + r < n; ++r) {
+    const double2 x = ld2(w[i0 + r]);
+    v[i0 + r] = st2<To>(make_double2(x.x * f, x.y * f));
+  }
 }
 
 template <class Ti, class To>
@@ -1097,8 +1148,16 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* _
   __syncthreads();
   // H s over the j x j leading block (column k has rows <= k + 1)
   if (t < q) {
+    // eight independent loads in flight per round instead of one
     double2 acc = zero;
-    for (int k = t > 0 ? t - 1 : 0; k < q; ++k) acc = cfma(Hraw[(int64_t)k * ld + t], ss[k], acc);
+    for (int k0 = t > 0 ? t - 1 : 0; k0 < q; k0 += 8) {
+      double2 h[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) h[u] = Hraw[(int64_t)min(k0 + u, q - 1) * ld + t];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < q) acc = cfma(h[u], ss[k0 + u], acc);
+    }
     hs[t] = acc;
   }
   if (t == 0 && j >= 1) {
@@ -1163,13 +1222,17 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double2* _
 
 // DCGS2 update, one read of V: v <- (v - V s) / rho (the finished basis
 // vector j, in place) and w <- w / rho - (kappa / rho) v - V g (the next
-// direction, in place), with rpart the per-block sums of |w|^2.
+// direction, in place), with rpart the per-block sums of |w|^2.  A thread
+// takes R = rows_of<VT>::R consecutive rows with 16-byte accesses (vec as in
+// k_mdot2) and the basis four vectors at a time.
 template <class VT, class T>
 __global__ __launch_bounds__(kThreads) void k_dcgs_update(int64_t n, const VT* __restrict__ V, int64_t ldv, int q,
                                                           const double2* __restrict__ coef, VT* __restrict__ v,
                                                           T* __restrict__ w, double* __restrict__ rpart,
                                                           int64_t vstride, int64_t wstride, int64_t cstride,
-                                                          const int* __restrict__ active) {
+                                                          const int* __restrict__ active, int vec) {
+  constexpr int R = rows_of<VT>::R;
+  static_assert(rows_of<T>::R == R, "basis and direction row groups differ");
   const int zs = blockIdx.z;
   if (active && !active[zs]) return;
   V += zs * vstride;
@@ -1179,28 +1242,90 @@ __global__ __launch_bounds__(kThreads) void k_dcgs_update(int64_t n, const VT* _
   rpart += (int64_t)zs * gridDim.x;
   __shared__ double2 cs_[kMaxRestart], cg_[kMaxRestart];
   __shared__ double sh[4];
+  const double us = basis_unscale<VT>();
   if (threadIdx.x < q) {
-    cs_[threadIdx.x] = coef[threadIdx.x];
-    cg_[threadIdx.x] = coef[kMaxRestart + threadIdx.x];
+    // the basis is read unscaled: fold the factor into the coefficients
+    const double2 a = coef[threadIdx.x], b = coef[kMaxRestart + threadIdx.x];
+    cs_[threadIdx.x] = make_double2(a.x * us, a.y * us);
+    cg_[threadIdx.x] = make_double2(b.x * us, b.y * us);
   }
   __syncthreads();
   const double ir = coef[2 * kMaxRestart].x;
   const double2 bv = coef[2 * kMaxRestart + 1];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 vi = ld2(v[i]), wi = ld2(w[i]);
-    double2 qa = make_double2(0.0, 0.0), ga = make_double2(0.0, 0.0);
-    for (int k = 0; k < q; ++k) {
-      const double2 x = ld2(V[(int64_t)k * ldv + i]);
-      qa = cfma(x, cs_[k], qa);
-      ga = cfma(x, cg_[k], ga);
+  for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; i0 < n;
+       i0 += (int64_t)gridDim.x * blockDim.x * R) {
+    double2 vi[R], wi[R], qa[R], ga[R];
+    const bool fast = vec && i0 + R <= n;
+    if (fast) {
+      ld_rows(v + i0, vi);
+      ld_rows(w + i0, wi);
+#pragma unroll
+      for (int r = 0; r < R; ++r) vi[r] = make_double2(vi[r].x * us, vi[r].y * us);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vi[r] = i0 + r < n ? ld2(v[i0 + r]) : make_double2(0.0, 0.0);
+        wi[r] = i0 + r < n ? ld2(w[i0 + r]) : make_double2(0.0, 0.0);
+      }
     }
-    v[i] = st2<VT>(make_double2((vi.x - qa.x) * ir, (vi.y - qa.y) * ir));
-    const double2 bvi = cmul(bv, vi);
-    const T ws = st2<T>(make_double2(wi.x * ir + bvi.x - ga.x, wi.y * ir + bvi.y - ga.y));
-    w[i] = ws;
-    const double2 wr = ld2(ws);
-    acc = fma(wr.x, wr.x, fma(wr.y, wr.y, acc));
+#pragma unroll
+    for (int r = 0; r < R; ++r) qa[r] = ga[r] = make_double2(0.0, 0.0);
+    if (fast) {
+      int k = 0;
+      for (; k + 4 <= q; k += 4) {
+        double2 x[4][R];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ld_rows(V + (int64_t)(k + u) * ldv + i0, x[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            qa[r] = cfma(x[u][r], cs_[k + u], qa[r]);
+            ga[r] = cfma(x[u][r], cg_[k + u], ga[r]);
+          }
+      }
+      for (; k < q; ++k) {
+        double2 x[R];
+        ld_rows(V + (int64_t)k * ldv + i0, x);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          qa[r] = cfma(x[r], cs_[k], qa[r]);
+          ga[r] = cfma(x[r], cg_[k], ga[r]);
+        }
+      }
+    } else {
+      for (int k = 0; k < q; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (i0 + r < n) {
+            const double2 x = raw2(V[(int64_t)k * ldv + i0 + r]);
+            qa[r] = cfma(x, cs_[k], qa[r]);
+            ga[r] = cfma(x, cg_[k], ga[r]);
+          }
+    }
+    double2 vo[R], wo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      vo[r] = make_double2((vi[r].x - qa[r].x) * ir, (vi[r].y - qa[r].y) * ir);
+      const double2 bvi = cmul(bv, vi[r]);
+      // |w|^2 of the value as stored
+      wo[r] = ld2(st2<T>(make_double2(wi[r].x * ir + bvi.x - ga[r].x, wi[r].y * ir + bvi.y - ga[r].y)));
+    }
+    if (fast) {
+      st_rows(v + i0, vo);
+      st_rows(w + i0, wo);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (i0 + r < n) {
+          v[i0 + r] = st2<VT>(vo[r]);
+          w[i0 + r] = st2<T>(wo[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (i0 + r < n) acc = fma(wo[r].x, wo[r].x, fma(wo[r].y, wo[r].y, acc));
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) rpart[blockIdx.x] = acc;
@@ -1628,7 +1753,7 @@ void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, con
   k_block_apply<T, MT, RT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
 }
 int mdot2_parts(int64_t n) {
-  const int64_t tiles = (n + kDot2Rows - 1) / kDot2Rows;
+  const int64_t tiles = (n + 2 * kThreads - 1) / (2 * kThreads);     // tiles of the smallest row groups
   return (int)(tiles < kDot2MaxBlocks ? (tiles > 0 ? tiles : 1) : kDot2MaxBlocks);
 }
 int mdot_parts(int64_t n) { return (int)((n + 2 * kThreads - 1) / (2 * kThreads)); }
@@ -1646,9 +1771,15 @@ void launch_norm2(int64_t n, const T* w, double* partial, double* out_norm, hipS
   k_norm2_partial<T><<<kRedBlocks, kThreads, 0, st>>>(n, w, partial, 0, nullptr);
   k_norm2_final<<<1, kThreads, 0, st>>>(partial, out_norm, nullptr, nullptr);
 }
+// every vector 16-byte aligned and the system strides multiples of R rows
+int vec_ok(int R, const void* a, const void* b, int64_t sa, int64_t sb) {
+  return (((uintptr_t)a | (uintptr_t)b) & 15) == 0 && sa % R == 0 && sb % R == 0;
+}
 template <class Ti, class To>
 void launch_scale_by_inv(int64_t n, const Ti* w, const double* norm, To* v, hipStream_t st) {
-  k_scale_by_inv<Ti, To><<<blocks_for(n), kThreads, 0, st>>>(n, w, norm, v, 0, 0, nullptr);
+  constexpr int R = scale_rows<Ti, To>();
+  k_scale_by_inv<Ti, To><<<blocks_for((n + R - 1) / R), kThreads, 0, st>>>(n, w, norm, v, 0, 0, nullptr,
+                                                                           vec_ok(R, w, v, 0, 0));
 }
 template <class Ti, class To>
 void launch_scale_host(int64_t n, const Ti* w, double a, To* v, hipStream_t st) {
@@ -1662,11 +1793,20 @@ template <class T>
 void launch_axpy(int64_t n, const T* z, double2* x, hipStream_t st) {
   k_axpy<T><<<blocks_for(n), kThreads, 0, st>>>(n, z, x, 0, 0, nullptr);
 }
+// whether the row-group accesses of k_mdot2 / k_dcgs_update may be used:
+// every vector of every system 16-byte aligned
+template <class VT>
+int rows_aligned(const void* V, const void* v, const void* w, int64_t ldv, int64_t vstride, int64_t wstride) {
+  constexpr int R = rows_of<VT>::R;
+  return (((uintptr_t)V | (uintptr_t)v | (uintptr_t)w) & 15) == 0 && ldv % R == 0 && vstride % R == 0 &&
+         wstride % R == 0;
+}
 template <class VT, class T>
 void launch_mdot2(int64_t n, const VT* V, int64_t ldv, int q, const VT* v, const T* w, double2* partial,
                   hipStream_t st) {
   dim3 grid(mdot2_parts(n), q > 0 ? (q + 7) / 8 : 1);
-  k_mdot2<VT, T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, 0, 0, 0, nullptr);
+  k_mdot2<VT, T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, 0, 0, 0, nullptr,
+                                            rows_aligned<VT>(V, v, w, ldv, 0, 0));
 }
 void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
                       double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
@@ -1694,14 +1834,16 @@ void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall,
 template <class VT, class T>
 void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double2* coef, VT* v, T* w, double* rpart,
                         double* out_norm, hipStream_t st) {
-  k_dcgs_update<VT, T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, 0, 0, 0, nullptr);
+  k_dcgs_update<VT, T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, 0, 0, 0, nullptr,
+                                                        rows_aligned<VT>(V, v, w, ldv, 0, 0));
   k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, nullptr, nullptr);
 }
 template <class VT, class T>
 void launch_mdot2_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const VT* v, const T* w,
                     int64_t wstride, double2* partial, int64_t pstride, const int* active, int nrhs, hipStream_t st) {
   dim3 grid(mdot2_parts(n), q > 0 ? (q + 7) / 8 : 1, nrhs);
-  k_mdot2<VT, T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, vstride, wstride, pstride, active);
+  k_mdot2<VT, T><<<grid, kThreads, 0, st>>>(n, V, ldv, q, v, w, partial, vstride, wstride, pstride, active,
+                                            rows_aligned<VT>(V, v, w, ldv, vstride, wstride));
 }
 void launch_dcgs_coef_b(int j, int m, const double2* dots, int64_t dstride, double2* Hraw, const double* tnorm,
                         double2* coef, double2* H, double* cs, double2* sn, double2* g, const double* beta,
@@ -1713,8 +1855,8 @@ template <class VT, class T>
 void launch_dcgs_update_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
                           int64_t cstride, VT* v, T* w, int64_t wstride, double* rpart, double* out_norm,
                           const int* active, int nrhs, hipStream_t st) {
-  k_dcgs_update<VT, T><<<dim3(kRedBlocks, 1, nrhs), kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, vstride, wstride,
-                                                                  cstride, active);
+  k_dcgs_update<VT, T><<<dim3(kRedBlocks, 1, nrhs), kThreads, 0, st>>>(
+      n, V, ldv, q, coef, v, w, rpart, vstride, wstride, cstride, active, rows_aligned<VT>(V, v, w, ldv, vstride, wstride));
   k_norm2_final<<<dim3(1, 1, nrhs), kThreads, 0, st>>>(rpart, out_norm, nullptr, active);
 }
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
@@ -1752,8 +1894,10 @@ void launch_norm2_b(int64_t n, const T* w, int64_t wstride, double* partial, dou
 template <class Ti, class To>
 void launch_scale_by_inv_b(int64_t n, const Ti* w, int64_t wstride, const double* norm, To* v, int64_t vstride,
                            const int* active, int nrhs, hipStream_t st) {
-  dim3 grid(blocks_for(n), 1, nrhs);
-  k_scale_by_inv<Ti, To><<<grid, kThreads, 0, st>>>(n, w, norm, v, wstride, vstride, active);
+  constexpr int R = scale_rows<Ti, To>();
+  dim3 grid(blocks_for((n + R - 1) / R), 1, nrhs);
+  k_scale_by_inv<Ti, To><<<grid, kThreads, 0, st>>>(n, w, norm, v, wstride, vstride, active,
+                                                    vec_ok(R, w, v, wstride, vstride));
 }
 void launch_givens_b(int j, int m, const double2* h1, const double2* h2, int64_t hstride, int64_t h2stride,
                      const double* nrm, double2* H, double* cs, double2* sn, double2* g, const double* beta,
