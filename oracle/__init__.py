@@ -35,5 +35,7 @@ PINS = {
     "blocks.rcb_blocks": "pinned: partition invariants (cover, sizes, spatial split)",
     "solve.direct": "pinned: dense numpy.linalg.solve on tiny meshes; residual",
     "solve.gmres": "pinned: agreement with the direct solve; residual history",
+    "ibc.*": "pinned: triangle quadrature, surface de Rham identities, thin-sheet limit of a volume layer, "
+             "convergence to a resolved volume plate (Leontovich limit) against wrong-normal / real-coefficient mutations",
     "post.*": "pinned: Bessel cylinder closed form, energy identity, reciprocity, passivity, h-convergence",
 }

@@ -17,6 +17,11 @@ W = int w_e . grad l_n (all tetrahedra), B_sigma = int sigma w_e . grad l_n,
 S_sigma = int sigma grad l_m . grad l_n, N_sigma = int sigma l_m l_n,
 D0 = lumped P1 mass (|K|/4 per vertex).  The right-hand side is
 int J . w_e for a current that is constant per tetrahedron.
+
+Optional surface-conductor triangles with complex coefficients c_f (the
+impedance boundary condition of Eqs. 8-10 has c_f = 1/Z, oracle/ibc.py)
+add -i omega M_G, -B_G and (i/omega) S_G (coefficients included) to the
+three blocks; their nodes carry V.
 """
 from __future__ import annotations
 
@@ -27,6 +32,7 @@ import scipy.sparse as sp
 
 from .topology import Topology, build
 from .elements import element_matrices
+from .ibc import FACE_EDGES, face_matrices
 
 
 def _coo(rows, cols, vals, shape) -> sp.csr_matrix:
@@ -50,7 +56,10 @@ class System:
     D0: np.ndarray          # nv
     F: np.ndarray           # [nt, 6, 3] int w_l (global orientation)
     vol: np.ndarray
-    lumped_c: np.ndarray    # nc, lumped conductor mass per conductor node
+    lumped_c: np.ndarray    # nc, lumped conductor mass per conductor node (+ area/3 on surface nodes)
+    Msurf: sp.csr_matrix = None   # ne x ne, complex: sum_f c_f int_f w_e . w_f
+    Bsurf: sp.csr_matrix = None   # ne x nc, complex: sum_f c_f int_f w_e . grad l_n
+    Ssurf: sp.csr_matrix = None   # nc x nc, complex: sum_f c_f int_f grad l_m . grad l_n
 
     @property
     def ndof(self) -> int:
@@ -64,6 +73,10 @@ class System:
         M11 = (self.K - 1j * self.omega * self.Msig).tocsr()
         M12 = (-self.Bsig).tocsr()
         M22 = ((1j / self.omega) * self.Ssig + self.delta_v * self.Nsig).tocsr()
+        if self.Msurf is not None:
+            M11 = (M11 - 1j * self.omega * self.Msurf).tocsr()
+            M12 = (M12 - self.Bsurf).tocsr()
+            M22 = (M22 + (1j / self.omega) * self.Ssurf).tocsr()
         return M11, M12, M22
 
     def matrix_no_gauge(self) -> sp.csr_matrix:
@@ -94,6 +107,9 @@ class System:
         Wsq = self.W.multiply(self.W)
         d[:ne] = self.K.diagonal() - 1j * self.omega * self.Msig.diagonal() + self.tau * (Wsq @ (1.0 / self.D0))
         d[ne:] = (1j / self.omega) * self.Ssig.diagonal() + self.delta_v * self.Nsig.diagonal()
+        if self.Msurf is not None:
+            d[:ne] -= 1j * self.omega * self.Msurf.diagonal()
+            d[ne:] += (1j / self.omega) * self.Ssurf.diagonal()
         return d
 
     def rhs(self, J: np.ndarray) -> np.ndarray:
@@ -105,15 +121,21 @@ class System:
         return b
 
 
-def assemble(xyz, tet, region, nu, sigma, omega, tau=1.0, delta_v=0.0, conductor_regions=None) -> System:
-    """Assemble the A-V system on the mesh with per-region nu (=1/mu) and sigma."""
+def assemble(xyz, tet, region, nu, sigma, omega, tau=1.0, delta_v=0.0, conductor_regions=None,
+             faces=None, face_coef=None) -> System:
+    """Assemble the A-V system on the mesh with per-region nu (=1/mu) and
+    sigma; faces [nf, 3] (node ids, any order) with complex face_coef [nf]
+    are surface conductors."""
     tet = np.asarray(tet, dtype=np.int64)
     region = np.asarray(region)
     nu = np.asarray(nu, dtype=float)
     sigma = np.asarray(sigma, dtype=float)
     if conductor_regions is None:
         conductor_regions = [r for r in range(sigma.size) if sigma[r] > 0]
-    topo = build(tet, xyz.shape[0], region, conductor_regions)
+    if faces is not None:
+        faces = np.sort(np.asarray(faces, dtype=np.int64), axis=1)
+        face_coef = np.asarray(face_coef, dtype=complex)
+    topo = build(tet, xyz.shape[0], region, conductor_regions, faces)
     ne, nv, nc = topo.ne, topo.nv, topo.nc
     el = element_matrices(xyz, tet)
     s = topo.sign                                       # [nt, 6]
@@ -141,5 +163,24 @@ def assemble(xyz, tet, region, nu, sigma, omega, tau=1.0, delta_v=0.0, conductor
     D0 = np.bincount(tet.ravel(), weights=np.repeat(el["vol"] / 4.0, 4), minlength=nv)
     lumped_c = np.bincount(vloc.ravel(), weights=np.repeat(el["vol"][ct] / 4.0, 4), minlength=nc)
     F = s[:, :, None] * el["F"]
-    return System(topo, float(omega), float(tau), float(delta_v), K, Msig, W, Bsig, Ssig, Nsig,
+    sysm = System(topo, float(omega), float(tau), float(delta_v), K, Msig, W, Bsig, Ssig, Nsig,
                   D0, F, el["vol"], lumped_c)
+    if faces is not None and faces.shape[0]:
+        fm = face_matrices(xyz, faces)
+        ekey = topo.edges[:, 0] * nv + topo.edges[:, 1]
+        fe = faces[:, FACE_EDGES]                                   # [nf, 3, 2], lo < hi
+        fkey = fe[..., 0] * nv + fe[..., 1]
+        f2e = np.searchsorted(ekey, fkey)
+        if np.any(f2e >= ne) or np.any(ekey[np.minimum(f2e, ne - 1)] != fkey):
+            raise ValueError("a surface triangle edge is not an edge of the mesh")
+        nf = faces.shape[0]
+        c = face_coef[:, None, None]
+        r3 = np.broadcast_to(f2e[:, :, None], (nf, 3, 3))
+        c3 = np.broadcast_to(f2e[:, None, :], (nf, 3, 3))
+        fv = topo.vmap[faces]
+        sysm.Msurf = _coo(r3, c3, c * fm["M"], (ne, ne))
+        sysm.Bsurf = _coo(r3, np.broadcast_to(fv[:, None, :], (nf, 3, 3)), c * fm["B"], (ne, nc))
+        sysm.Ssurf = _coo(np.broadcast_to(fv[:, :, None], (nf, 3, 3)), np.broadcast_to(fv[:, None, :], (nf, 3, 3)),
+                          c * fm["S"], (nc, nc))
+        sysm.lumped_c = lumped_c + np.bincount(fv.ravel(), weights=np.repeat(fm["area"] / 3.0, 3), minlength=nc)
+    return sysm

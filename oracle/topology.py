@@ -1,7 +1,8 @@
 """Mesh topology for the A-V unknowns (oracle).
 
 A lives on the edges of the triangulation (lowest-order Nedelec), V on the
-nodes of the conducting sub-mesh (P1), cf. the discrete spaces of Section 3.
+nodes of the conducting sub-mesh (P1), cf. the discrete spaces of Section 3,
+and on the nodes of impedance-boundary triangles (Eqs. 8-10, oracle/ibc.py).
 Edges are the sorted node pairs (lo, hi), numbered in lexicographic order and
 oriented from the lower to the higher global node id.  Conductor nodes are
 numbered in increasing global id.  DOF order: [A on edges ; V on conductor
@@ -44,7 +45,9 @@ class Topology:
         return self.ne + self.nc
 
 
-def build(tet: np.ndarray, nv: int, region: np.ndarray, conductor_regions) -> Topology:
+def build(tet: np.ndarray, nv: int, region: np.ndarray, conductor_regions, faces=None) -> Topology:
+    """faces: optional [nf, 3] surface-conductor triangles; their nodes carry V
+    and they join conductor components like conducting tetrahedra."""
     tet = np.asarray(tet, dtype=np.int64)
     nt = tet.shape[0]
     pairs = tet[:, LOCAL_EDGES]                          # [nt, 6, 2] local (a, b)
@@ -57,16 +60,18 @@ def build(tet: np.ndarray, nv: int, region: np.ndarray, conductor_regions) -> To
     sign = np.where(pairs[..., 0] < pairs[..., 1], 1.0, -1.0)
 
     cond_tet = np.isin(region, np.asarray(list(conductor_regions)))
-    cond_nodes = np.unique(tet[cond_tet])
+    faces = np.zeros((0, 3), dtype=np.int64) if faces is None else np.asarray(faces, dtype=np.int64)
+    cond_nodes = np.unique(np.concatenate([tet[cond_tet].ravel(), faces.ravel()]))
     vmap = -np.ones(nv, dtype=np.int64)
     vmap[cond_nodes] = np.arange(cond_nodes.size)
 
-    # connected components of the conducting sub-mesh (tets sharing a node)
+    # connected components of the conducting sub-mesh (tets and surface
+    # triangles sharing a node)
     ct = tet[cond_tet]
-    if ct.size:
-        loc = vmap[ct]
-        rows = np.repeat(loc[:, 0], 3)
-        cols = loc[:, 1:].ravel()
+    if ct.size or faces.size:
+        loc, flo = vmap[ct], vmap[faces]
+        rows = np.concatenate([np.repeat(loc[:, 0], 3), np.repeat(flo[:, 0], 2)])
+        cols = np.concatenate([loc[:, 1:].ravel(), flo[:, 1:].ravel()])
         g = sp.coo_matrix((np.ones(rows.size), (rows, cols)), shape=(cond_nodes.size,) * 2)
         ncomp, comp = connected_components(g, directed=False)
     else:

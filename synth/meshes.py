@@ -78,6 +78,32 @@ def cube(n: int, lo: float = 0.25, hi: float = 0.75, length: float = 1.0) -> Mes
     return Mesh(xyz, tet, region, ["air", "conductor"], {"family": "cube", "n": n})
 
 
+def box(x, y, z) -> Mesh:
+    """Tensor-product grid with node coordinates x, y, z (increasing), each
+    cell split into 6 tetrahedra as in cube(); region 0 everywhere (callers
+    set regions from the centroids)."""
+    x, y, z = (np.asarray(a, dtype=np.float64) for a in (x, y, z))
+    nx, ny, nz = x.size, y.size, z.size
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    xyz = np.stack([x[i.ravel()], y[j.ravel()], z[k.ravel()]], axis=1)
+
+    def nid(ii, jj, kk):
+        return ii + nx * (jj + ny * kk)
+
+    ci, cj, ck = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), np.arange(nz - 1), indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    tets = []
+    for p in perms:
+        off = np.zeros((4, 3), dtype=np.int64)
+        for s in range(1, 4):
+            off[s] = off[s - 1]
+            off[s, p[s - 1]] += 1
+        tets.append(np.stack([nid(ci + off[s, 0], cj + off[s, 1], ck + off[s, 2]) for s in range(4)], axis=1))
+    tet = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int32)
+    return Mesh(xyz, tet, np.zeros(tet.shape[0], dtype=np.int32), ["air"], {"family": "box"})
+
+
 # ---------------------------------------------------------------------------
 # 2-D ring triangulations
 # ---------------------------------------------------------------------------
