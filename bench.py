@@ -271,8 +271,10 @@ def main():
         dom = max(single, key=lambda k: single[k]["total_ms"])
         d = single[dom]
         kname = knames[dom] + ktypes[head]
-        if dom == "block_apply" and head == "mixed16":
-            kname = "k_block_apply<float2, unsigned int>"
+        if dom == "block_apply":      # storage of the vector, the inverses, the input
+            kname = {"fp64": "k_block_apply<double2, double2, double2>",
+                     "mixed": "k_block_apply<float2, float2, float2>",
+                     "mixed16": "k_block_apply<float2, unsigned int, hbasis>"}[head]
         roof = {"bound": "hbm", "kernel": kname, "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["frac"], "traffic": measured_traffic(kname),
                 "algorithmic_bytes": d["bytes_per_launch"]}

@@ -89,7 +89,9 @@ typedef struct {
   int32_t iters;       /* Arnoldi steps taken                                      */
   int32_t restarts;    /* completed cycles                                         */
   int32_t converged;   /* 1 if the true weighted residual met tol                  */
-  int32_t breakdown;   /* 1 if a happy breakdown ended a cycle                     */
+  int32_t breakdown;   /* 1 if a zero residual estimate ended the solve: the cycle
+                          that produced it did not reduce the true residual (a
+                          zero estimate with progress only restarts)             */
   double relres;       /* true weighted relative residual of the returned x        */
   double est_relres;   /* Arnoldi estimate at exit                                 */
   double seconds;      /* wall time of the call                                    */
@@ -133,6 +135,40 @@ typedef struct {
 eddy_status eddy_mesh_create(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet,
                              const int32_t* region, int32_t nreg, const int32_t* is_conductor,
                              eddy_mesh** out);
+/* eddy_mesh_create_ibc: as eddy_mesh_create, plus nf impedance-boundary
+ * triangles face[nf*3] (host, node ids, any order) with face_region[nf]
+ * (host): the impedance boundary condition of Section 2, Eqs. 8-10, on the
+ * boundary Gamma_p of a plate that is not meshed.  With Z = (1 - i) /
+ * (delta sigma) and delta = sqrt(2 / (omega mu sigma)) of the face's
+ * region (sigma, nu = 1/mu as given at eddy_op_assemble), the plate enters
+ * as a surface conductor of coefficient 1/Z: M11 gains -i omega (1/Z) int
+ * w_e . w_f, M12 = M21^T gains -(1/Z) int w_e . grad l_n and M22 gains
+ * (i/omega)(1/Z) int grad l_m . grad l_n over the triangles (tangential
+ * traces, surface gradients).  V lives on the triangles' nodes, which join
+ * conductor components like conducting tetrahedra (lumped weights |T|/3).
+ * Every face region must be flagged conducting; every triangle edge must
+ * be an edge of the tetrahedra.  Errors as eddy_mesh_create, plus
+ * EDDY_ERR_ARG for face indices or regions and EDDY_ERR_MESH for repeated
+ * nodes or an edge not in the mesh.  eddy_ibc_split builds such a mesh. */
+eddy_status eddy_mesh_create_ibc(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet,
+                                 const int32_t* region, int32_t nreg, const int32_t* is_conductor,
+                                 int64_t nf, const int32_t* face, const int32_t* face_region,
+                                 eddy_mesh** out);
+/* eddy_ibc_split (host only): remove the tetrahedra of the regions with
+ * is_ibc[r] != 0 and return the rest with its nodes renumbered in
+ * increasing old id (node_map[nv]: new id or -1), and the interface
+ * triangles (faces of a removed tetrahedron that are also faces of a kept
+ * one; node triples increasing, in lexicographic order) with the region of
+ * the removed tetrahedron.  Call once with every output array NULL to get
+ * nv_out, nt_out, nf_out, then with arrays of those sizes (xyz_out
+ * [nv_out*3], tet_out [nt_out*4], region_out [nt_out], face_out [nf_out*3],
+ * face_region_out [nf_out], node_map [nv]); all caller-owned.  Errors:
+ * EDDY_ERR_ARG (sizes, indices, some but not all outputs NULL). */
+eddy_status eddy_ibc_split(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet,
+                           const int32_t* region, int32_t nreg, const int32_t* is_ibc, int64_t* nv_out,
+                           int64_t* nt_out, int64_t* nf_out, double* xyz_out, int32_t* tet_out,
+                           int32_t* region_out, int32_t* face_out, int32_t* face_region_out,
+                           int32_t* node_map);
 void eddy_mesh_destroy(eddy_mesh* mesh);
 /* Counts: edges, conductor nodes, nnz of the stored M (structural pattern of
  * all element couplings, gauge excluded), nnz of W, conductor components. */

@@ -56,6 +56,8 @@ using namespace eddy;
 
 struct eddy_op {
   int64_t nv, nt, ne, nc, nct, n, nnz, nnzw, nb, ns, nsell;
+  int64_t nf;                         // impedance-boundary triangles
+  int *face, *face_region;
   int32_t nreg, ncomp, bsize;
   uint64_t geom_hash;
   double tau, tau_p, delta_v, omega = 0;
@@ -120,6 +122,8 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->region = c.take<int>(m->nt);
   o->cidx = c.take<int>(m->nt);
   o->signbits = c.take<uint8_t>(m->nt);
+  o->face = c.take<int>(m->nf * 3);
+  o->face_region = c.take<int>(m->nf);
   o->edge_v = c.take<int>(m->ne * 2);
   o->comp = c.take<int>(m->nc);
   o->edges = c.take<int>(m->ne * 2);
@@ -162,7 +166,7 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->lval = c.take<double>((int64_t)m->lcol.size());
   o->ldiag = c.take<double>(m->nv);
   o->val = c.take<double2>(m->nnz());
-  o->ebuf = c.take<double2>(21 * m->nt + 34 * m->nct);
+  o->ebuf = c.take<double2>(21 * m->nt + 34 * m->nct + 21 * m->nf);
   o->minv = c.take<double2>(nb * kMaxBlock * kMaxBlock);
   o->gscr = c.take<double>(nb * kMaxBlock * kMaxBlock);
   o->val32 = c.take<float2>(m->nnz());
@@ -171,7 +175,7 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->wval = c.take<double>(m->nnzw());
   o->wtval = c.take<double>(m->nnzw());
   o->wbuf = c.take<double>(24 * m->nt);
-  o->vol4 = c.take<double>(m->nt);
+  o->vol4 = c.take<double>(m->nt + m->nf);
   o->rbuf = c.take<double>(6 * m->nt);
   o->d0 = c.take<double>(m->nv);
   o->d0tau = c.take<double>(m->nv);
@@ -213,6 +217,10 @@ uint64_t geometry_hash(const eddy_mesh* m) {
   mix(m->xyz.data(), sizeof(double) * m->xyz.size());
   mix(m->tet.data(), sizeof(int32_t) * m->tet.size());
   mix(m->region.data(), sizeof(int32_t) * m->region.size());
+  if (m->nf) {
+    mix(m->face.data(), sizeof(int32_t) * m->face.size());
+    mix(m->face_region.data(), sizeof(int32_t) * m->face_region.size());
+  }
   return h;
 }
 
@@ -307,7 +315,17 @@ const char* eddy_status_string(eddy_status s) {
 
 eddy_status eddy_mesh_create(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet, const int32_t* region,
                              int32_t nreg, const int32_t* is_conductor, eddy_mesh** out) {
+  return eddy_mesh_create_ibc(nv, xyz, nt, tet, region, nreg, is_conductor, 0, nullptr, nullptr, out);
+}
+
+eddy_status eddy_mesh_create_ibc(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet,
+                                 const int32_t* region, int32_t nreg, const int32_t* is_conductor, int64_t nf,
+                                 const int32_t* face, const int32_t* face_region, eddy_mesh** out) {
   if (!out || !xyz || !tet || !region || !is_conductor) { set_error("NULL argument"); return EDDY_ERR_ARG; }
+  if (nf < 0 || (nf > 0 && (!face || !face_region)) || nf * 3 >= INT32_MAX) {
+    set_error("bad face arguments");
+    return EDDY_ERR_ARG;
+  }
   *out = nullptr;
   if (nv < 4 || nt < 1 || nreg < 1 || nv >= INT32_MAX || nt * 6 >= INT32_MAX) {
     set_error("mesh sizes out of range");
@@ -323,6 +341,12 @@ eddy_status eddy_mesh_create(int64_t nv, const double* xyz, int64_t nt, const in
     m->tet.assign(tet, tet + nt * 4);
     m->region.assign(region, region + nt);
     m->is_cond.assign(is_conductor, is_conductor + nreg);
+    m->nf = nf;
+    if (nf) {
+      m->face.assign(face, face + nf * 3);
+      m->face_region.assign(face_region, face_region + nf);
+      for (int64_t f = 0; f < nf; ++f) std::sort(&m->face[3 * f], &m->face[3 * f] + 3);
+    }
     m->geom_hash = geometry_hash(m);
     eddy_status st = build_mesh(m);
     if (st != EDDY_OK) { delete m; return st; }
@@ -406,6 +430,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   carve_op(o, (char*)dev_ws, m);
   o->bytes = need;
   o->nv = m->nv; o->nt = m->nt; o->ne = m->ne; o->nc = m->nc; o->nct = m->nct; o->n = m->ndof();
+  o->nf = m->nf;
   o->nnz = m->nnz(); o->nnzw = m->nnzw(); o->nb = (int64_t)m->blk_ptr.size() - 1;
   o->nreg = m->nreg; o->ncomp = m->ncomp; o->bsize = p->block_size;
   o->geom_hash = m->geom_hash;
@@ -426,6 +451,7 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
 #define UP(dst, src) if (r == EDDY_OK) r = upload(dst, src, s)
   UP(o->xyz, m->xyz); UP(o->tet, m->tet); UP(o->region, m->region); UP(o->cidx, m->cidx);
   UP(o->signbits, m->signbits); UP(o->edge_v, m->edge_v); UP(o->comp, m->comp);
+  UP(o->face, m->face); UP(o->face_region, m->face_region);
   UP(o->edges, m->edges); UP(o->cond_nodes, m->cond_nodes); UP(o->tet2edge, m->tet2edge); UP(o->vmap, m->vmap);
   UP(o->rowptr, m->rowptr); UP(o->col, m->col); UP(o->diagpos, m->diagpos); UP(o->cptr, m->cptr);
   UP(o->clist, m->clist); UP(o->wrowptr, m->wrowptr); UP(o->wcol, m->wcol); UP(o->wcptr, m->wcptr);
@@ -496,6 +522,8 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   HIP_TRY(hipMemsetAsync(o->status, 0, sizeof(int) * 4, s));
   launch_element(o->nt, o->nct, o->xyz, o->tet, o->region, o->signbits, o->cidx, o->nu_reg, o->sig_reg, omega,
                  o->delta_v, o->ebuf, o->wbuf, o->vol4, s);
+  launch_face(o->nf, o->xyz, o->face, o->face_region, o->nu_reg, o->sig_reg, omega,
+              o->ebuf + 21 * o->nt + 34 * o->nct, o->vol4 + o->nt, s);
   launch_gather_c(o->nnz, o->cptr, o->clist, o->ebuf, o->val, s);
   launch_gather_r(o->nnzw, o->wcptr, o->wclist, o->wbuf, o->wval, s);
   launch_gather_r(o->nv, o->d0ptr, o->d0list, o->vol4, o->d0, s);
@@ -940,7 +968,13 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
     }
     ++cyc;
     if (R.relres <= opts->tol || it >= opts->max_iter) break;
-    if (stop && R.breakdown) break;
+    if (stop && R.breakdown) {
+      // a zero estimate with an unconverged true residual was rounding (the
+      // Pythagorean rho cancelled near the attainable accuracy): restart as
+      // long as the cycle still reduced the true residual
+      if (!(R.relres < rel_start)) break;
+      R.breakdown = 0;
+    }
     r = W.w;
   }
   return EDDY_OK;
@@ -1247,10 +1281,17 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     HIP_TRY(hipStreamSynchronize(s));
     for (int r = 0; r < nrhs; ++r) {
       if (!cyc[r]) continue;
+      const double before = beta[r];
       beta[r] = nr[r];
       R[r].restarts++;
       R[r].relres = beta[r] / bnorm[r];
-      if (R[r].relres <= opts->tol || its[r] >= opts->max_iter || (R[r].breakdown && kc[r] < m)) done[r] = 1;
+      if (R[r].relres <= opts->tol || its[r] >= opts->max_iter) done[r] = 1;
+      else if (R[r].breakdown && kc[r] < m) {
+        // as in the single solve: a breakdown with an unconverged true
+        // residual restarts while the cycle made progress
+        if (!(beta[r] < before)) done[r] = 1;
+        else R[r].breakdown = 0;
+      }
     }
     rvec = B.w64;
   }

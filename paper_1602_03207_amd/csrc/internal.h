@@ -69,6 +69,10 @@ inline int pair6(int l, int m) {    // upper-triangle slot of a symmetric 6x6
   if (l > m) { int t = l; l = m; m = t; }
   return l * 6 - (l * (l - 1)) / 2 + (m - l);
 }
+inline int pair3(int i, int j) {    // upper-triangle slot of a symmetric 3x3
+  if (i > j) { int t = i; i = j; j = t; }
+  return i == 0 ? j : (i == 1 ? 2 + j : 5);
+}
 inline int pair4(int i, int j) {    // upper-triangle slot of a symmetric 4x4
   if (i > j) { int t = i; i = j; j = t; }
   return i * 4 - (i * (i - 1)) / 2 + (j - i);
@@ -85,7 +89,12 @@ struct eddy_mesh {
   std::vector<int32_t> tet;         // nt*4
   std::vector<int32_t> region;      // nt
   std::vector<int32_t> is_cond;     // nreg
-  uint64_t geom_hash = 0;           // FNV-1a over xyz, tet and region (same geometry <=> same hash)
+  // impedance-boundary triangles (surface conductors, Eqs. 8-10): node ids
+  // increasing per triangle, the region whose sigma and nu give 1/Z, and the
+  // edges of the local pairs (0,1), (0,2), (1,2)
+  int64_t nf = 0;
+  std::vector<int32_t> face, face_region, face2edge;
+  uint64_t geom_hash = 0;           // FNV-1a over xyz, tet, region and faces (same geometry <=> same hash)
   // topology
   int64_t ne = 0, nc = 0, nct = 0;
   int32_t ncomp = 0;

@@ -148,6 +148,10 @@ void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);
 void launch_backsolve(int k, int m, const double2* H, const double2* g, double2* y, hipStream_t st);
+// impedance-boundary triangles: surface-conductor values into fbuf (21 nf
+// slots, see k_face) and |T|/3 into area3
+void launch_face(int64_t nf, const double* xyz, const int* face, const int* face_region, const double* nu_reg,
+                 const double* sig_reg, double omega, double2* fbuf, double* area3, hipStream_t st);
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st);
 void launch_zero(int64_t n, double2* x, hipStream_t st);
 void launch_vmean(int64_t nc, int ncomp, const int* comp, const double* lumped, double2* V, double2* scratch,

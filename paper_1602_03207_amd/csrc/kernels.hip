@@ -126,6 +126,97 @@ __global__ __launch_bounds__(kThreads) void k_element(int64_t nt, int64_t nct, c
   }
 }
 
+// ---------------------------------------------------------------------------
+// Impedance-boundary triangles (Section 2, Eqs. 8-10).  The plate removed
+// from the mesh enters as a surface conductor on its boundary Gamma_p with
+// the coefficient c = 1/Z = delta sigma / (1 - i), delta = sqrt(2 nu /
+// (omega sigma)) its skin depth, i.e. the volume terms with sigma dV
+// replaced by c dS:
+//   AA = -i omega c M_lm,   AV = -c B_lk,   VV = (i / omega) c S_ij,
+//   M_lm = |T|/12 [(1+d_ac) G_bd - (1+d_ad) G_bc - (1+d_bc) G_ad + (1+d_bd) G_ac],
+//   B_lk = |T|/3 (G_bk - G_ak),  S_ij = |T| G_ij,  G_ij = grad l_i . grad l_j,
+// with the surface gradients grad l_i = n x (p_(i+2) - p_(i+1)) / (2|T|) and
+// local edges (0,1), (0,2), (1,2) running from the lower to the higher node
+// id (the nodes of a face are stored increasing).  Slots: AA at q * nf + f
+// (q the upper-triangle pair), AV at 6 nf + (l * 3 + k) * nf + f, VV at
+// 15 nf + q * nf + f; area3[f] = |T|/3 (lumped V weight).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_face(int64_t nf, const double* __restrict__ xyz,
+                                                   const int* __restrict__ face,
+                                                   const int* __restrict__ face_region,
+                                                   const double* __restrict__ nu_reg,
+                                                   const double* __restrict__ sig_reg, double omega,
+                                                   double2* __restrict__ fbuf, double* __restrict__ area3) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  double p[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) p[k][j] = xyz[3 * (int64_t)face[3 * f + k] + j];
+  double e1[3], e2[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    e1[j] = p[1][j] - p[0][j];
+    e2[j] = p[2][j] - p[0][j];
+  }
+  const double cn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const double two_a = sqrt(cn[0] * cn[0] + cn[1] * cn[1] + cn[2] * cn[2]);
+  const double area = 0.5 * two_a;
+  const double nh[3] = {cn[0] / two_a, cn[1] / two_a, cn[2] / two_a};
+  double g[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double* a = p[(i + 1) % 3];
+    const double* b = p[(i + 2) % 3];
+    const double d[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    g[i][0] = (nh[1] * d[2] - nh[2] * d[1]) / two_a;
+    g[i][1] = (nh[2] * d[0] - nh[0] * d[2]) / two_a;
+    g[i][2] = (nh[0] * d[1] - nh[1] * d[0]) / two_a;
+  }
+  double G[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G[i][k] = g[i][0] * g[k][0] + g[i][1] * g[k][1] + g[i][2] * g[k][2];
+  const int reg = face_region[f];
+  const double sig = sig_reg[reg], nu = nu_reg[reg];
+  const double delta = sqrt(2.0 * nu / (omega * sig));
+  const double cr = 0.5 * delta * sig, ci = 0.5 * delta * sig;     // delta sigma / (1 - i)
+  constexpr int ea[3] = {0, 0, 1};
+  constexpr int eb[3] = {1, 2, 2};
+  const double a12 = area * (1.0 / 12.0);
+  int q = 0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int m = l; m < 3; ++m) {
+      const int a = ea[l], b = eb[l], c = ea[m], d = eb[m];
+      const double M = a12 * ((a == c ? 2.0 : 1.0) * G[b][d] - (a == d ? 2.0 : 1.0) * G[b][c] -
+                              (b == c ? 2.0 : 1.0) * G[a][d] + (b == d ? 2.0 : 1.0) * G[a][c]);
+      fbuf[(int64_t)q * nf + f] = make_double2(omega * ci * M, -omega * cr * M);
+      ++q;
+    }
+  const double a3 = area * (1.0 / 3.0);
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double B = a3 * (G[eb[l]][k] - G[ea[l]][k]);
+      fbuf[(int64_t)(6 + l * 3 + k) * nf + f] = make_double2(-cr * B, -ci * B);
+    }
+  q = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const double S = area * G[i][j];
+      fbuf[(int64_t)(15 + q) * nf + f] = make_double2(-ci * S / omega, cr * S / omega);
+      ++q;
+    }
+  area3[f] = a3;
+}
+
 // out[i] = sum of buf[list[p]] for p in [ptr[i], ptr[i+1]), in list order.
 __global__ __launch_bounds__(kThreads) void k_gather_c(int64_t n, const int* __restrict__ ptr,
                                                        const int* __restrict__ list, const double2* __restrict__ buf,
@@ -2021,6 +2112,11 @@ __global__ __launch_bounds__(kThreads) void k_to_c16(int64_t n, const double2* _
 }
 void launch_to_c16(int64_t n, const double2* in, uint32_t* out, hipStream_t st) {
   k_to_c16<<<blocks_for(n), kThreads, 0, st>>>(n, in, out);
+}
+void launch_face(int64_t nf, const double* xyz, const int* face, const int* face_region, const double* nu_reg,
+                 const double* sig_reg, double omega, double2* fbuf, double* area3, hipStream_t st) {
+  if (nf <= 0) return;
+  k_face<<<blocks_for(nf), kThreads, 0, st>>>(nf, xyz, face, face_region, nu_reg, sig_reg, omega, fbuf, area3);
 }
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st) {
   k_diag_scale<<<blocks_for(n), kThreads, 0, st>>>(n, in, s, divide, out, 0, 0);

@@ -199,6 +199,20 @@ eddy_status build_mesh(eddy_mesh* m) {
     });
     if (bad.load() >= 0) { set_error("degenerate tetrahedron " + std::to_string(bad.load())); return EDDY_ERR_MESH; }
   }
+  // ---- impedance-boundary triangles: node ids increasing, conducting region
+  const int64_t nf = m->nf;
+  for (int64_t f = 0; f < nf; ++f) {
+    int32_t* fn = &m->face[3 * f];
+    for (int k = 0; k < 3; ++k)
+      if (fn[k] < 0 || fn[k] >= nv) { set_error("face node index out of range"); return EDDY_ERR_ARG; }
+    std::sort(fn, fn + 3);
+    if (fn[0] == fn[1] || fn[1] == fn[2]) { set_error("degenerate face " + std::to_string(f)); return EDDY_ERR_MESH; }
+    const int32_t r = m->face_region[f];
+    if (r < 0 || r >= m->nreg || !m->is_cond[r]) {
+      set_error("face region out of range or not flagged conducting (face " + std::to_string(f) + ")");
+      return EDDY_ERR_ARG;
+    }
+  }
   // ---- edges: group local edges by their low node, sort each group by the high node
   std::vector<int32_t> lo(nt * 6), hi(nt * 6);
   m->signbits.assign(nt, 0);
@@ -231,6 +245,30 @@ eddy_status build_mesh(eddy_mesh* m) {
     m->ne = eid;
   }
   const int64_t ne = m->ne;
+  // local edges (0,1), (0,2), (1,2) of each face: edges are numbered by low
+  // node, then high node, so a binary search inside the low node's run
+  {
+    std::vector<int32_t> first(nv + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) first[m->edges[2 * e] + 1]++;
+    for (int64_t a = 0; a < nv; ++a) first[a + 1] += first[a];
+    m->face2edge.assign(nf * 3, -1);
+    constexpr int fa[3] = {0, 0, 1}, fb[3] = {1, 2, 2};
+    for (int64_t f = 0; f < nf; ++f)
+      for (int l = 0; l < 3; ++l) {
+        const int32_t a = m->face[3 * f + fa[l]], b = m->face[3 * f + fb[l]];
+        int32_t lo = first[a], hi = first[a + 1];
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) / 2;
+          if (m->edges[2 * mid + 1] < b) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo >= first[a + 1] || m->edges[2 * lo + 1] != b) {
+          set_error("an edge of face " + std::to_string(f) + " is not an edge of the tetrahedra");
+          return EDDY_ERR_MESH;
+        }
+        m->face2edge[3 * f + l] = lo;
+      }
+  }
   // ---- conductor maps
   m->cidx.assign(nt, -1);
   m->vmap.assign(nv, -1);
@@ -240,6 +278,7 @@ eddy_status build_mesh(eddy_mesh* m) {
       m->cidx[t] = (int32_t)nct++;
       for (int k = 0; k < 4; ++k) m->vmap[T[4 * t + k]] = 0;
     }
+  for (int64_t i = 0; i < nf * 3; ++i) m->vmap[m->face[i]] = 0;     // V on impedance surfaces
   m->nct = nct;
   m->cond_nodes.clear();
   for (int64_t n = 0; n < nv; ++n)
@@ -261,6 +300,13 @@ eddy_status build_mesh(eddy_mesh* m) {
           if (rk != r0) par[std::max(rk, r0)] = std::min(rk, r0), r0 = std::min(rk, r0);
         }
       }
+    for (int64_t f = 0; f < nf; ++f) {
+      int32_t r0 = find_root(par, m->vmap[m->face[3 * f]]);
+      for (int k = 1; k < 3; ++k) {
+        int32_t rk = find_root(par, m->vmap[m->face[3 * f + k]]);
+        if (rk != r0) par[std::max(rk, r0)] = std::min(rk, r0), r0 = std::min(rk, r0);
+      }
+    }
     m->comp.assign(nc, -1);
     std::vector<int32_t> label(nc, -1);
     int32_t nl = 0;
@@ -295,8 +341,17 @@ eddy_status build_mesh(eddy_mesh* m) {
   std::vector<int32_t> vptr, vitem;
   group_by(vkeys, nc, vptr, vitem);
   for (auto& x : vitem) x = vsrc[x];   // -> 4*t + k, increasing t per node
-  // ---- M pattern + scatter lists
+  // face occurrences: edge -> 3*f + l, V node -> 3*f + k (increasing f)
+  std::vector<int32_t> feptr, feocc, fvptr, fvocc;
+  group_by(m->face2edge, ne, feptr, feocc);
+  {
+    std::vector<int32_t> fv(nf * 3);
+    for (int64_t i = 0; i < nf * 3; ++i) fv[i] = m->vmap[m->face[i]];
+    group_by(fv, nc, fvptr, fvocc);
+  }
+  // ---- M pattern + scatter lists (slots: tetrahedra AA, AV, VV, then faces AA, AV, VV)
   const int64_t AV0 = 21 * nt, VV0 = 21 * nt + 24 * nct;
+  const int64_t FA0 = 21 * nt + 34 * nct, FAV0 = FA0 + 6 * nf, FVV0 = FAV0 + 9 * nf;
   auto genM = [&](int64_t r, std::vector<std::pair<int32_t, int32_t>>& out) {
     if (r < ne) {
       for (int32_t p = eptr[r]; p < eptr[r + 1]; ++p) {
@@ -309,6 +364,14 @@ eddy_status build_mesh(eddy_mesh* m) {
           for (int k = 0; k < 4; ++k)
             out.emplace_back((int32_t)(ne + m->vmap[T[4 * t + k]]), (int32_t)(AV0 + (l * 4 + k) * nct + c));
       }
+      for (int32_t p = feptr[r]; p < feptr[r + 1]; ++p) {
+        const int64_t f = feocc[p] / 3;
+        const int l = feocc[p] % 3;
+        for (int mm = 0; mm < 3; ++mm)
+          out.emplace_back(m->face2edge[3 * f + mm], (int32_t)(FA0 + pair3(l, mm) * nf + f));
+        for (int k = 0; k < 3; ++k)
+          out.emplace_back((int32_t)(ne + m->vmap[m->face[3 * f + k]]), (int32_t)(FAV0 + (l * 3 + k) * nf + f));
+      }
     } else {
       int64_t n = r - ne;
       for (int32_t p = vptr[n]; p < vptr[n + 1]; ++p) {
@@ -320,9 +383,18 @@ eddy_status build_mesh(eddy_mesh* m) {
         for (int kk = 0; kk < 4; ++kk)
           out.emplace_back((int32_t)(ne + m->vmap[T[4 * t + kk]]), (int32_t)(VV0 + pair4(k, kk) * nct + c));
       }
+      for (int32_t p = fvptr[n]; p < fvptr[n + 1]; ++p) {
+        const int64_t f = fvocc[p] / 3;
+        const int k = fvocc[p] % 3;
+        for (int mm = 0; mm < 3; ++mm)
+          out.emplace_back(m->face2edge[3 * f + mm], (int32_t)(FAV0 + (mm * 3 + k) * nf + f));
+        for (int kk = 0; kk < 3; ++kk)
+          out.emplace_back((int32_t)(ne + m->vmap[m->face[3 * f + kk]]), (int32_t)(FVV0 + pair3(k, kk) * nf + f));
+      }
     }
   };
-  if (21 * nt + 34 * nct >= (int64_t)INT32_MAX || 24 * nt >= (int64_t)INT32_MAX) {
+  if (21 * nt + 34 * nct + 21 * nf >= (int64_t)INT32_MAX || 24 * nt >= (int64_t)INT32_MAX ||
+      nt + nf >= (int64_t)INT32_MAX) {
     set_error("mesh too large for 32-bit scatter indices");
     return EDDY_ERR_ARG;
   }
@@ -383,9 +455,16 @@ eddy_status build_mesh(eddy_mesh* m) {
     group_by(m->tet, nv, m->d0ptr, item);
     m->d0list.resize(item.size());
     for (size_t i = 0; i < item.size(); ++i) m->d0list[i] = item[i] / 4;
-    m->lcptr = vptr;
-    m->lclist.resize(vitem.size());
-    for (size_t i = 0; i < vitem.size(); ++i) m->lclist[i] = vitem[i] / 4;
+    // lumped V-node weights: |K|/4 of conducting tets (vol4[t]), then
+    // |T|/3 of impedance triangles (vol4[nt + f])
+    m->lcptr.assign(nc + 1, 0);
+    m->lclist.clear();
+    m->lclist.reserve(vitem.size() + fvocc.size());
+    for (int64_t n = 0; n < nc; ++n) {
+      for (int32_t p = vptr[n]; p < vptr[n + 1]; ++p) m->lclist.push_back(vitem[p] / 4);
+      for (int32_t p = fvptr[n]; p < fvptr[n + 1]; ++p) m->lclist.push_back((int32_t)(nt + fvocc[p] / 3));
+      m->lcptr[n + 1] = (int32_t)m->lclist.size();
+    }
     m->rptr = eptr;
     m->rlist.resize(eocc.size());
     for (size_t i = 0; i < eocc.size(); ++i) {
@@ -487,3 +566,93 @@ eddy_status build_subdomains(eddy_mesh* m, int32_t b, std::vector<int32_t>& sub_
 }
 
 }  // namespace eddy
+
+// ---- impedance boundary: remove the tetrahedra of the flagged regions and
+// return their interface with the rest as surface triangles (Section 2,
+// Eqs. 8-10).  Faces are sorted node triples; the interface is the set of
+// faces of removed tetrahedra that are also faces of kept ones.
+extern "C" eddy_status eddy_ibc_split(int64_t nv, const double* xyz, int64_t nt, const int32_t* tet,
+                                      const int32_t* region, int32_t nreg, const int32_t* is_ibc, int64_t* nv_out,
+                                      int64_t* nt_out, int64_t* nf_out, double* xyz_out, int32_t* tet_out,
+                                      int32_t* region_out, int32_t* face_out, int32_t* face_region_out,
+                                      int32_t* node_map) {
+  using namespace eddy;
+  if (!xyz || !tet || !region || !is_ibc || !nv_out || !nt_out || !nf_out) {
+    set_error("NULL argument");
+    return EDDY_ERR_ARG;
+  }
+  if (nv < 1 || nt < 1 || nreg < 1 || nv >= INT32_MAX || nt * 4 >= INT32_MAX) {
+    set_error("mesh sizes out of range");
+    return EDDY_ERR_ARG;
+  }
+  const bool fill = xyz_out || tet_out || region_out || face_out || face_region_out || node_map;
+  if (fill && !(xyz_out && tet_out && region_out && face_out && face_region_out && node_map)) {
+    set_error("either all output arrays or none");
+    return EDDY_ERR_ARG;
+  }
+  try {
+    for (int64_t i = 0; i < nt * 4; ++i)
+      if (tet[i] < 0 || tet[i] >= nv) { set_error("tet node index out of range"); return EDDY_ERR_ARG; }
+    for (int64_t t = 0; t < nt; ++t)
+      if (region[t] < 0 || region[t] >= nreg) { set_error("region id out of range"); return EDDY_ERR_ARG; }
+    struct Face {
+      int32_t n[3], reg;
+      bool operator<(const Face& o) const {
+        return n[0] != o.n[0] ? n[0] < o.n[0] : n[1] != o.n[1] ? n[1] < o.n[1] : n[2] < o.n[2];
+      }
+      bool same(const Face& o) const { return n[0] == o.n[0] && n[1] == o.n[1] && n[2] == o.n[2]; }
+    };
+    constexpr int tf[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+    std::vector<Face> kept, gone;
+    std::vector<char> used(nv, 0);
+    int64_t ntk = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      const bool g = is_ibc[region[t]] != 0;
+      if (!g) {
+        ++ntk;
+        for (int k = 0; k < 4; ++k) used[tet[4 * t + k]] = 1;
+      }
+      for (auto& q : tf) {
+        Face f;
+        for (int k = 0; k < 3; ++k) f.n[k] = tet[4 * t + q[k]];
+        std::sort(f.n, f.n + 3);
+        f.reg = region[t];
+        (g ? gone : kept).push_back(f);
+      }
+    }
+    std::sort(kept.begin(), kept.end());
+    std::sort(gone.begin(), gone.end());
+    std::vector<Face> iface;
+    for (size_t i = 0; i < gone.size(); ++i) {
+      if (i > 0 && gone[i].same(gone[i - 1])) continue;
+      auto it = std::lower_bound(kept.begin(), kept.end(), gone[i]);
+      if (it != kept.end() && it->same(gone[i])) iface.push_back(gone[i]);
+    }
+    int64_t nvk = 0;
+    std::vector<int32_t> map(nv, -1);
+    for (int64_t n = 0; n < nv; ++n)
+      if (used[n]) map[n] = (int32_t)nvk++;
+    *nv_out = nvk;
+    *nt_out = ntk;
+    *nf_out = (int64_t)iface.size();
+    if (!fill) return EDDY_OK;
+    std::copy(map.begin(), map.end(), node_map);
+    for (int64_t n = 0; n < nv; ++n)
+      if (map[n] >= 0)
+        for (int j = 0; j < 3; ++j) xyz_out[3 * (int64_t)map[n] + j] = xyz[3 * n + j];
+    int64_t o = 0;
+    for (int64_t t = 0; t < nt; ++t)
+      if (!is_ibc[region[t]]) {
+        for (int k = 0; k < 4; ++k) tet_out[4 * o + k] = map[tet[4 * t + k]];
+        region_out[o++] = region[t];
+      }
+    for (size_t f = 0; f < iface.size(); ++f) {
+      for (int k = 0; k < 3; ++k) face_out[3 * f + k] = map[iface[f].n[k]];
+      face_region_out[f] = iface[f].reg;
+    }
+  } catch (const std::exception& e) {
+    set_error(std::string("host failure: ") + e.what());
+    return EDDY_ERR_ARG;
+  }
+  return EDDY_OK;
+}

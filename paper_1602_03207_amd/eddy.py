@@ -47,7 +47,7 @@ class _Report(C.Structure):
 
 
 EXPORTS = [
-    "eddy_mesh_create", "eddy_mesh_destroy", "eddy_mesh_counts", "eddy_mesh_edges",
+    "eddy_mesh_create", "eddy_mesh_create_ibc", "eddy_ibc_split", "eddy_mesh_destroy", "eddy_mesh_counts", "eddy_mesh_edges",
     "eddy_mesh_conductor_nodes", "eddy_mesh_blocks", "eddy_op_workspace_bytes", "eddy_op_create",
     "eddy_op_destroy", "eddy_op_assemble", "eddy_rhs_from_current", "eddy_solve_workspace_bytes",
     "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched", "eddy_impedance", "eddy_delta_z_volume",
@@ -65,6 +65,9 @@ def _load():
     P, I32, I64, D, VP = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
     sig = {
         "eddy_mesh_create": [I64, P(D), I64, P(I32), P(I32), I32, P(I32), P(VP)],
+        "eddy_mesh_create_ibc": [I64, P(D), I64, P(I32), P(I32), I32, P(I32), I64, P(I32), P(I32), P(VP)],
+        "eddy_ibc_split": [I64, P(D), I64, P(I32), P(I32), I32, P(I32), P(I64), P(I64), P(I64), P(D), P(I32), P(I32),
+                           P(I32), P(I32), P(I32)],
         "eddy_mesh_destroy": [VP],
         "eddy_mesh_counts": [VP, P(I64), P(I64), P(I64), P(I64), P(I32)],
         "eddy_mesh_edges": [VP, P(I32)],
@@ -173,19 +176,49 @@ def delta_z_volume(op_defect, x_defect, op_free, x_free, currents_k, currents_l)
     return dZ
 
 
-class Mesh:
-    """Host mesh handle: tetrahedra, regions, conductor flags per region."""
+def ibc_split(xyz, tet, region, is_ibc):
+    """eddy_ibc_split: the mesh without the tetrahedra of the flagged regions
+    and its interface triangles with them.  Returns a dict with xyz, tet,
+    region, faces, face_region, node_map."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tet = np.ascontiguousarray(tet, dtype=np.int32)
+    region = np.ascontiguousarray(region, dtype=np.int32)
+    flags = np.ascontiguousarray(np.asarray(is_ibc).astype(np.int32))
+    nv, nt = xyz.shape[0], tet.shape[0]
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    args = (nv, _ptr(xyz, C.c_double), nt, _ptr(tet, C.c_int32), _ptr(region, C.c_int32), flags.size,
+            _ptr(flags, C.c_int32), C.byref(a), C.byref(b), C.byref(c))
+    nul = [None] * 6
+    _check(_lib.eddy_ibc_split(*args, *nul), "eddy_ibc_split")
+    out = {"xyz": np.empty((a.value, 3)), "tet": np.empty((b.value, 4), np.int32),
+           "region": np.empty(b.value, np.int32), "faces": np.empty((c.value, 3), np.int32),
+           "face_region": np.empty(c.value, np.int32), "node_map": np.empty(nv, np.int32)}
+    _check(_lib.eddy_ibc_split(*args, _ptr(out["xyz"], C.c_double), _ptr(out["tet"], C.c_int32),
+                               _ptr(out["region"], C.c_int32), _ptr(out["faces"], C.c_int32),
+                               _ptr(out["face_region"], C.c_int32), _ptr(out["node_map"], C.c_int32)),
+           "eddy_ibc_split")
+    return out
 
-    def __init__(self, xyz, tet, region, is_conductor):
+
+class Mesh:
+    """Host mesh handle: tetrahedra, regions, conductor flags per region, and
+    optional impedance-boundary triangles (faces [nf, 3], face_region [nf])."""
+
+    def __init__(self, xyz, tet, region, is_conductor, faces=None, face_region=None):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.tet = np.ascontiguousarray(tet, dtype=np.int32)
         self.region = np.ascontiguousarray(region, dtype=np.int32)
         self.is_conductor = np.ascontiguousarray(np.asarray(is_conductor).astype(np.int32))
+        self.faces = np.ascontiguousarray(np.zeros((0, 3)) if faces is None else faces, dtype=np.int32)
+        self.face_region = np.ascontiguousarray(np.zeros(0) if face_region is None else face_region, dtype=np.int32)
+        self.nf = self.faces.shape[0]
         h = C.c_void_p()
-        _check(_lib.eddy_mesh_create(self.xyz.shape[0], _ptr(self.xyz, C.c_double), self.tet.shape[0],
-                                     _ptr(self.tet, C.c_int32), _ptr(self.region, C.c_int32),
-                                     self.is_conductor.size, _ptr(self.is_conductor, C.c_int32), C.byref(h)),
-               "eddy_mesh_create")
+        _check(_lib.eddy_mesh_create_ibc(self.xyz.shape[0], _ptr(self.xyz, C.c_double), self.tet.shape[0],
+                                         _ptr(self.tet, C.c_int32), _ptr(self.region, C.c_int32),
+                                         self.is_conductor.size, _ptr(self.is_conductor, C.c_int32), self.nf,
+                                         _ptr(self.faces, C.c_int32) if self.nf else None,
+                                         _ptr(self.face_region, C.c_int32) if self.nf else None, C.byref(h)),
+               "eddy_mesh_create_ibc")
         self._h = h
         ne, nc, nnz, nnzw, ncomp = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
         _check(_lib.eddy_mesh_counts(h, C.byref(ne), C.byref(nc), C.byref(nnz), C.byref(nnzw), C.byref(ncomp)),
