@@ -242,6 +242,27 @@ eddy_status eddy_solve_batched_workspace_bytes(const eddy_op* op, int32_t nrhs, 
 eddy_status eddy_solve_batched(eddy_op* op, int32_t nrhs, const eddy_c128* b_dev, eddy_c128* x_dev,
                                const eddy_solve_opts* opts, void* ws, size_t ws_bytes, eddy_solve_report* rep,
                                eddy_stream stream);
+/* eddy_solve_multifreq: the batched solve for systems of different
+ * frequencies (Section 4: probe positions times frequencies of one scan).
+ * ops[nops]: operators of one mesh, block size and material set assembled
+ * at different omega; system r (right-hand side r of b_dev [nrhs][ndof],
+ * solution r of x_dev) belongs to ops[op_of_rhs[r]] (host, nondecreasing).
+ * On the penalty-free operator every entry is P + c(omega) Q with P, Q real
+ * (c = -i omega on A-A entries, i / omega on V-V entries, 0 on the
+ * couplings), so the inner SpMV reads one frequency-factored copy of the
+ * matrix (built from ops[0] in the workspace) for all systems, each scaled
+ * by its own operator's equilibration; block inverses, the FP64 true
+ * residual and the post-processing are each system's own operator's.
+ * Requirements as eddy_solve_batched, plus: precision >= 1 and no
+ * impedance-boundary faces when more than one operator is used (1/Z scales
+ * with sqrt(omega)).  Workspace: eddy_solve_multifreq_workspace_bytes.
+ * Errors: EDDY_ERR_ARG (mismatched operators, unordered op_of_rhs, the
+ * requirements), EDDY_ERR_WORKSPACE, as eddy_solve_batched otherwise. */
+eddy_status eddy_solve_multifreq_workspace_bytes(eddy_op* const* ops, int32_t nops, int32_t nrhs,
+                                                 const eddy_solve_opts* opts, size_t* bytes);
+eddy_status eddy_solve_multifreq(eddy_op* const* ops, int32_t nops, int32_t nrhs, const int32_t* op_of_rhs,
+                                 const eddy_c128* b_dev, eddy_c128* x_dev, const eddy_solve_opts* opts,
+                                 void* ws, size_t ws_bytes, eddy_solve_report* rep, eddy_stream stream);
 
 /* ---- outputs -----------------------------------------------------------
  * Coil impedance Z[k*nsrc + l] (host) = -(i omega / (I_k I_l)) b_l^T A_k for

@@ -58,6 +58,7 @@ struct eddy_op {
   int64_t nv, nt, ne, nc, nct, n, nnz, nnzw, nb, ns, nsell;
   int64_t nf;                         // impedance-boundary triangles
   int *face, *face_region;
+  std::vector<double> nu_h, sig_h;    // materials of the last assembly (host)
   int32_t nreg, ncomp, bsize;
   uint64_t geom_hash;
   double tau, tau_p, delta_v, omega = 0;
@@ -517,6 +518,8 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   }
   hipStream_t s = (hipStream_t)stream;
   o->omega = omega;
+  o->nu_h.assign(nu, nu + o->nreg);
+  o->sig_h.assign(sigma, sigma + o->nreg);
   HIP_TRY(hipMemcpyAsync(o->nu_reg, nu, sizeof(double) * o->nreg, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(o->sig_reg, sigma, sizeof(double) * o->nreg, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(o->status, 0, sizeof(int) * 4, s));
@@ -1103,9 +1106,23 @@ struct BatchWs {
   double2 *Hraw, *dots, *coef, *zeros;
   double* tnorm;
   ProjBufs P;
+  // several frequencies: factored matrix, scaled SpMV input, per-system data
+  float2 *pq = nullptr, *u = nullptr;
+  mf_sys* sys = nullptr;
 };
 
-size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, int precision) {
+// Systems of a batch grouped by operator: group g holds the systems
+// [start[g], start[g + 1]) of operator op[g].  One group is
+// eddy_solve_batched; several (operators of one mesh and one material set
+// at different frequencies) is eddy_solve_multifreq, whose inner SpMV reads
+// the frequency-factored matrix once for all of them.
+struct Groups {
+  std::vector<eddy_op*> op;
+  std::vector<int> start;
+  int count() const { return (int)op.size(); }
+};
+
+size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, int precision, bool multi = false) {
   Carve c(base);
   const int64_t n = o->n, ld = basis_ld(n), nv = o->nv, ne = o->ne;
   const size_t tb = precision >= 1 ? sizeof(float2) : sizeof(double2);
@@ -1151,6 +1168,11 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
   P.nrm = c.take<double>(8);
   P.xtmp = c.take<double2>(n);
   P.wtmp = c.take<double2>(n);
+  if (multi) {
+    B->pq = c.take<float2>(o->nnz);
+    B->u = c.take<float2>((int64_t)nrhs * ld);
+    B->sys = c.take<mf_sys>(nrhs);
+  }
   return c.off + 256;
 }
 
@@ -1158,8 +1180,9 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
 // SpMV and block-Jacobi launches serve every active system at once.
 // VT: storage of the basis (T, or hbasis with T = float2)
 template <class T, class VT>
-eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std::vector<double>& bnorm,
-                        std::vector<int>& its, std::vector<eddy_solve_report>& R, hipStream_t s) {
+eddy_status run_batched(eddy_op* o, const Groups& G, BatchWs& B, const eddy_solve_opts* opts,
+                        std::vector<double>& bnorm, std::vector<int>& its, std::vector<eddy_solve_report>& R,
+                        hipStream_t s) {
   const int nrhs = B.nrhs, m = B.m;
   const int64_t n = o->n, ld = B.ld, vstride = (int64_t)(m + 1) * ld, hs = m + 2;
   const int64_t np = mdot_parts(n > o->nv ? n : o->nv);
@@ -1169,21 +1192,41 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
   T* wT = (T*)B.wT;
   T* zT = (T*)B.zT;
   const T* val = std::is_same<T, float2>::value ? (const T*)o->val32 : (const T*)o->val;
-  const T* minv = std::is_same<T, float2>::value ? (const T*)o->minv32 : (const T*)o->minv;
   const bool half_inv = opts->precision == 2;
+  const int ng = G.count();
+  // block-Jacobi apply, one launch per operator group (its own inverses)
   auto bapply = [&](int64_t rstride, const auto* r, const int* act) {
     using RT = std::remove_cv_t<std::remove_pointer_t<decltype(r)>>;
-    if constexpr (std::is_same<RT, hbasis>::value) {
-      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, o->minv16, nrhs, rstride, r, ld, zT, act, s);
-    } else {
-      if constexpr (std::is_same<T, float2>::value) {
-        if (half_inv) {
-          launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, o->minv16, nrhs, rstride, r, ld, zT, act, s);
-          return;
+    for (int g = 0; g < ng; ++g) {
+      const eddy_op* og = G.op[g];
+      const int g0 = G.start[g], gn = G.start[g + 1] - g0;
+      const RT* rg = r + (int64_t)g0 * rstride;
+      T* zg = zT + (int64_t)g0 * ld;
+      const int* ag = act ? act + g0 : nullptr;
+      const T* minv = std::is_same<T, float2>::value ? (const T*)og->minv32 : (const T*)og->minv;
+      if constexpr (std::is_same<RT, hbasis>::value) {
+        launch_block_apply_b(og->nb, og->blk_ptr, og->blk_dofs, og->minv16, gn, rstride, rg, ld, zg, ag, s);
+      } else {
+        bool done = false;
+        if constexpr (std::is_same<T, float2>::value) {
+          if (half_inv) {
+            launch_block_apply_b(og->nb, og->blk_ptr, og->blk_dofs, og->minv16, gn, rstride, rg, ld, zg, ag, s);
+            done = true;
+          }
         }
+        if (!done) launch_block_apply_b(og->nb, og->blk_ptr, og->blk_dofs, minv, gn, rstride, rg, ld, zg, ag, s);
       }
-      launch_block_apply_b(o->nb, o->blk_ptr, o->blk_dofs, minv, nrhs, rstride, r, ld, zT, act, s);
     }
+  };
+  // inner SpMV: the operator's own values for one group, the factored
+  // matrix for several
+  auto inner_spmv = [&]() {
+    if (ng == 1) {
+      launch_spmv_b(n, o->rowptr, o->col, val, nrhs, ld, (const T*)zT, (const T*)nullptr, wT, B.run, s);
+      return;
+    }
+    if constexpr (std::is_same<T, float2>::value)
+      launch_spmv_mf(n, o->ne, o->rowptr, o->col, B.pq, nrhs, ld, zT, B.u, wT, B.sys, B.run, s);
   };
   std::vector<int> done(nrhs, 0), run(nrhs), cyc(nrhs), kc(nrhs);
   std::vector<double> beta(bnorm), est((size_t)nrhs * (m + 1));
@@ -1210,7 +1253,7 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     for (int j = 0; j < m; ++j) {
       VT* vj = V + (int64_t)j * ld;
       bapply(vstride, (const VT*)vj, B.run);
-      launch_spmv_b(n, o->rowptr, o->col, val, nrhs, ld, (const T*)zT, (const T*)nullptr, wT, B.run, s);
+      inner_spmv();
       launch_mdot2_b(n, (const VT*)V, ld, vstride, j, (const VT*)vj, (const T*)wT, ld, B.part, pstride, B.run, nrhs,
                      s);
       launch_reduce_cols_b(2 * j + 2, nparts2, B.part, pstride, B.dots, dstride, nullptr, B.run, nrhs, s);
@@ -1273,8 +1316,13 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
     launch_combine_b(n, (const VT*)V, ld, vstride, B.kcols, B.yd, hs, wT, ld, B.cyc, nrhs, s);
     bapply(ld, (const T*)wT, B.cyc);
     launch_axpy_b(n, (const T*)zT, ld, B.xt, ld, B.cyc, nrhs, s);
-    // FP64 true residuals of the penalty-free operator
-    launch_spmv_b(n, o->rowptr, o->col, o->val, nrhs, ld, (const double2*)B.xt, (const double2*)B.bt, B.w64, B.cyc, s);
+    // FP64 true residuals of the penalty-free operators
+    for (int g = 0; g < ng; ++g) {
+      const eddy_op* og = G.op[g];
+      const int64_t o0 = (int64_t)G.start[g] * ld;
+      launch_spmv_b(n, og->rowptr, og->col, og->val, G.start[g + 1] - G.start[g], ld, (const double2*)B.xt + o0,
+                    (const double2*)B.bt + o0, B.w64 + o0, B.cyc + G.start[g], s);
+    }
     launch_norm2_b(n, (const double2*)B.w64, ld, B.rpart, B.nrm, B.cyc, nrhs, s);
     std::vector<double> nr(nrhs);
     HIP_TRY(hipMemcpyAsync(nr.data(), B.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
@@ -1298,6 +1346,94 @@ eddy_status run_batched(eddy_op* o, BatchWs& B, const eddy_solve_opts* opts, std
   return EDDY_OK;
 }
 
+// The batched solve over groups of systems (see Groups).
+eddy_status batched_core(const Groups& G, const eddy_c128* b_dev, eddy_c128* x_dev, const eddy_solve_opts* opts,
+                         void* ws, size_t ws_bytes, eddy_solve_report* rep, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  eddy_op* o = G.op[0];
+  const int nrhs = G.start.back(), ng = G.count();
+  for (int g = 0; g < ng; ++g) {
+    if (!G.op[g]->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+    if (G.op[g]->delta_v != 0.0) { set_error("the batched solve needs delta_V = 0"); return EDDY_ERR_ARG; }
+  }
+  eddy_status st = check_opts(opts);
+  if (st != EDDY_OK) return st;
+  BatchWs B;
+  const size_t need = carve_batch(&B, nullptr, o, nrhs, opts->restart, opts->precision, ng > 1);
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) {
+    set_error("batched solve workspace too small or misaligned: need " + std::to_string(need) + " bytes");
+    return EDDY_ERR_WORKSPACE;
+  }
+  carve_batch(&B, ws, o, nrhs, opts->restart, opts->precision, ng > 1);
+  const int64_t n = o->n, ld = B.ld;
+  std::vector<eddy_op*> op_of(nrhs);
+  for (int g = 0; g < ng; ++g)
+    for (int r = G.start[g]; r < G.start[g + 1]; ++r) op_of[r] = G.op[g];
+  if (ng > 1) {
+    // the factored matrix from the first operator, per-system scaling and Im c
+    launch_factor_pq(n, o->ne, o->rowptr, o->col, o->val, o->s, o->omega, B.pq, s);
+    std::vector<mf_sys> sh(nrhs);
+    for (int r = 0; r < nrhs; ++r)
+      sh[r] = mf_sys{op_of[r]->s, (float)(-op_of[r]->omega), (float)(1.0 / op_of[r]->omega)};
+    HIP_TRY(hipMemcpyAsync(B.sys, sh.data(), sizeof(mf_sys) * nrhs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  std::vector<eddy_solve_report> R(nrhs);
+  std::vector<double> bnorm(nrhs);
+  std::vector<int> its(nrhs, 0);
+  // every source must be divergence-free: the penalty-free operator is iterated
+  for (int r = 0; r < nrhs; ++r) {
+    const double2* br = (const double2*)b_dev + (int64_t)r * n;
+    launch_norm2(n, br, B.P.rpart, B.P.nrm, s);
+    double braw = 0, dn = 0;
+    HIP_TRY(hipMemcpyAsync(&braw, B.P.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    launch_edge_divergence(o->nv, op_of[r]->wtrowptr, op_of[r]->wtcol, o->edges, br, B.P.cr, s);
+    launch_norm2(o->nv, B.P.cr, B.P.rpart, B.P.nrm, s);
+    HIP_TRY(hipMemcpyAsync(&dn, B.P.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!std::isfinite(braw)) { set_error("right-hand side is not finite"); return EDDY_ERR_ARG; }
+    R[r].div_residual = braw > 0 ? dn / braw : 0.0;
+    if (R[r].div_residual > 1e-10) {
+      set_error("the batched solve needs divergence-free sources (system " + std::to_string(r) + ")");
+      return EDDY_ERR_ARG;
+    }
+  }
+  for (int g = 0; g < ng; ++g)
+    launch_diag_scale_b(n, (const double2*)b_dev + (int64_t)G.start[g] * n, n, G.op[g]->s, 0,
+                        B.bt + (int64_t)G.start[g] * ld, ld, G.start[g + 1] - G.start[g], s);
+  for (int r = 0; r < nrhs; ++r) launch_zero(n, B.xt + (int64_t)r * ld, s);
+  launch_norm2_b(n, (const double2*)B.bt, ld, B.rpart, B.nrm, nullptr, nrhs, s);
+  HIP_TRY(hipMemcpyAsync(bnorm.data(), B.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (opts->precision == 2) st = run_batched<float2, hbasis>(o, G, B, opts, bnorm, its, R, s);
+  else if (opts->precision == 1) st = run_batched<float2, float2>(o, G, B, opts, bnorm, its, R, s);
+  else st = run_batched<double2, double2>(o, G, B, opts, bnorm, its, R, s);
+  if (st != EDDY_OK) return st;
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    double2* xr = (double2*)x_dev + (int64_t)r * n;
+    eddy_op* orr = op_of[r];
+    if ((st = finish_solution(orr, B.P, B.xt + (int64_t)r * ld, B.bt + (int64_t)r * ld, xr, bnorm[r], false, R[r],
+                              s)) != EDDY_OK)
+      return st;
+    launch_vmean(orr->nc, orr->ncomp, orr->comp, orr->lumped, xr + orr->ne, orr->red, s);
+    R[r].iters = its[r];
+    R[r].reorth_steps = its[r];   // the delayed scheme reorthogonalises every basis vector
+    R[r].precision_used = opts->precision;
+    R[r].converged = R[r].relres <= opts->tol ? 1 : 0;
+    all = all && R[r].converged;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < nrhs; ++r) {
+    R[r].seconds = secs;
+    if (rep) rep[r] = R[r];
+  }
+  return all ? EDDY_OK : EDDY_WARN_NOT_CONVERGED;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1315,72 +1451,62 @@ eddy_status eddy_solve_batched_workspace_bytes(const eddy_op* o, int32_t nrhs, c
 eddy_status eddy_solve_batched(eddy_op* o, int32_t nrhs, const eddy_c128* b_dev, eddy_c128* x_dev,
                                const eddy_solve_opts* opts, void* ws, size_t ws_bytes, eddy_solve_report* rep,
                                eddy_stream stream) {
-  auto t0 = std::chrono::steady_clock::now();
   if (!o || !b_dev || !x_dev || nrhs < 1) { set_error("bad argument"); return EDDY_ERR_ARG; }
-  if (!o->assembled) { set_error("operator not assembled"); return EDDY_ERR_ARG; }
+  Groups G;
+  G.op = {o};
+  G.start = {0, nrhs};
+  return batched_core(G, b_dev, x_dev, opts, ws, ws_bytes, rep, (hipStream_t)stream);
+}
+
+eddy_status eddy_solve_multifreq_workspace_bytes(eddy_op* const* ops, int32_t nops, int32_t nrhs,
+                                                 const eddy_solve_opts* opts, size_t* bytes) {
+  if (!ops || nops < 1 || !ops[0] || !bytes || nrhs < 1) { set_error("bad argument"); return EDDY_ERR_ARG; }
   eddy_status st = check_opts(opts);
   if (st != EDDY_OK) return st;
   BatchWs B;
-  const size_t need = carve_batch(&B, nullptr, o, nrhs, opts->restart, opts->precision);
-  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) {
-    set_error("batched solve workspace too small or misaligned: need " + std::to_string(need) + " bytes");
-    return EDDY_ERR_WORKSPACE;
-  }
-  carve_batch(&B, ws, o, nrhs, opts->restart, opts->precision);
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t n = o->n, ld = B.ld;
-  if (o->delta_v != 0.0) { set_error("the batched solve needs delta_V = 0"); return EDDY_ERR_ARG; }
-  std::vector<eddy_solve_report> R(nrhs);
-  std::vector<double> bnorm(nrhs);
-  std::vector<int> its(nrhs, 0);
-  // every source must be divergence-free: the penalty-free operator is iterated
+  *bytes = carve_batch(&B, nullptr, ops[0], nrhs, opts->restart, opts->precision, nops > 1);
+  return EDDY_OK;
+}
+
+eddy_status eddy_solve_multifreq(eddy_op* const* ops, int32_t nops, int32_t nrhs, const int32_t* op_of_rhs,
+                                 const eddy_c128* b_dev, eddy_c128* x_dev, const eddy_solve_opts* opts, void* ws,
+                                 size_t ws_bytes, eddy_solve_report* rep, eddy_stream stream) {
+  if (!ops || nops < 1 || nrhs < 1 || !op_of_rhs || !b_dev || !x_dev) { set_error("bad argument"); return EDDY_ERR_ARG; }
+  for (int f = 0; f < nops; ++f)
+    if (!ops[f] || !ops[f]->assembled) { set_error("operator " + std::to_string(f) + " NULL or not assembled"); return EDDY_ERR_ARG; }
+  Groups G;
   for (int r = 0; r < nrhs; ++r) {
-    const double2* br = (const double2*)b_dev + (int64_t)r * n;
-    launch_norm2(n, br, B.P.rpart, B.P.nrm, s);
-    double braw = 0, dn = 0;
-    HIP_TRY(hipMemcpyAsync(&braw, B.P.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    launch_edge_divergence(o->nv, o->wtrowptr, o->wtcol, o->edges, br, B.P.cr, s);
-    launch_norm2(o->nv, B.P.cr, B.P.rpart, B.P.nrm, s);
-    HIP_TRY(hipMemcpyAsync(&dn, B.P.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (!std::isfinite(braw)) { set_error("right-hand side is not finite"); return EDDY_ERR_ARG; }
-    R[r].div_residual = braw > 0 ? dn / braw : 0.0;
-    if (R[r].div_residual > 1e-10) {
-      set_error("the batched solve needs divergence-free sources (system " + std::to_string(r) + ")");
+    const int f = op_of_rhs[r];
+    if (f < 0 || f >= nops || (r > 0 && f < op_of_rhs[r - 1])) {
+      set_error("op_of_rhs must be nondecreasing operator indices");
+      return EDDY_ERR_ARG;
+    }
+    if (r == 0 || f != op_of_rhs[r - 1]) {
+      G.op.push_back(ops[f]);
+      G.start.push_back(r);
+    }
+  }
+  G.start.push_back(nrhs);
+  const eddy_op* o0 = ops[0];
+  for (int f = 1; f < nops; ++f) {
+    const eddy_op* of = ops[f];
+    if (of->geom_hash != o0->geom_hash || of->n != o0->n || of->nnz != o0->nnz || of->nb != o0->nb ||
+        of->nu_h != o0->nu_h || of->sig_h != o0->sig_h) {
+      set_error("the operators must share the mesh, the block size and the materials (only omega may differ)");
       return EDDY_ERR_ARG;
     }
   }
-  launch_diag_scale_b(n, (const double2*)b_dev, n, o->s, 0, B.bt, ld, nrhs, s);
-  for (int r = 0; r < nrhs; ++r) launch_zero(n, B.xt + (int64_t)r * ld, s);
-  launch_norm2_b(n, (const double2*)B.bt, ld, B.rpart, B.nrm, nullptr, nrhs, s);
-  HIP_TRY(hipMemcpyAsync(bnorm.data(), B.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (opts->precision == 2) st = run_batched<float2, hbasis>(o, B, opts, bnorm, its, R, s);
-  else if (opts->precision == 1) st = run_batched<float2, float2>(o, B, opts, bnorm, its, R, s);
-  else st = run_batched<double2, double2>(o, B, opts, bnorm, its, R, s);
-  if (st != EDDY_OK) return st;
-  bool all = true;
-  for (int r = 0; r < nrhs; ++r) {
-    double2* xr = (double2*)x_dev + (int64_t)r * n;
-    if ((st = finish_solution(o, B.P, B.xt + (int64_t)r * ld, B.bt + (int64_t)r * ld, xr, bnorm[r], false, R[r], s)) !=
-        EDDY_OK)
-      return st;
-    launch_vmean(o->nc, o->ncomp, o->comp, o->lumped, xr + o->ne, o->red, s);
-    R[r].iters = its[r];
-    R[r].reorth_steps = its[r];   // the delayed scheme reorthogonalises every basis vector
-    R[r].precision_used = opts->precision;
-    R[r].converged = R[r].relres <= opts->tol ? 1 : 0;
-    all = all && R[r].converged;
+  if (G.count() > 1) {
+    if (o0->nf > 0) {
+      set_error("impedance-boundary faces depend on sqrt(omega): no frequency-factored matrix");
+      return EDDY_ERR_ARG;
+    }
+    if (!opts || opts->precision < 1) {
+      set_error("several frequencies in one batch need precision >= 1 (complex64 inner process)");
+      return EDDY_ERR_ARG;
+    }
   }
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(s));
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  for (int r = 0; r < nrhs; ++r) {
-    R[r].seconds = secs;
-    if (rep) rep[r] = R[r];
-  }
-  return all ? EDDY_OK : EDDY_WARN_NOT_CONVERGED;
+  return batched_core(G, b_dev, x_dev, opts, ws, ws_bytes, rep, (hipStream_t)stream);
 }
 
 eddy_status eddy_profile(eddy_op* o, int32_t enable, double* ms, int64_t* counts) {

@@ -148,6 +148,18 @@ void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);
 void launch_backsolve(int k, int m, const double2* H, const double2* g, double2* y, hipStream_t st);
+// several frequencies in one batch (see k_spmv_mf): per system the
+// equilibration of its operator and Im c on the A rows (-omega) and V rows
+// (1/omega)
+struct mf_sys {
+  const double* s;
+  float w_a, w_v;
+};
+void launch_factor_pq(int64_t n, int64_t ne, const int* rowptr, const int* col, const double2* val, const double* s,
+                      double omega, float2* pq, hipStream_t st);
+// y_r = s_r (P + c_r Q)(s_r x_r); u is scratch of the shape of x
+void launch_spmv_mf(int64_t n, int64_t ne, const int* rowptr, const int* col, const float2* pq, int nrhs, int64_t ld,
+                    const float2* x, float2* u, float2* y, const mf_sys* sys, const int* active, hipStream_t st);
 // impedance-boundary triangles: surface-conductor values into fbuf (21 nf
 // slots, see k_face) and |T|/3 into area3
 void launch_face(int64_t nf, const double* xyz, const int* face, const int* face_region, const double* nu_reg,

@@ -1551,6 +1551,94 @@ __global__ __launch_bounds__(kThreads) void k_spmv_b(int64_t n, const int* __res
   }
 }
 
+// ---- several frequencies in one batch.  On the penalty-free operator every
+// stored entry is P + c(omega) Q with P, Q real: c = -i omega on the A-A
+// entries (K_nu - i omega M_sigma), c = i / omega on the V-V entries
+// ((i/omega) S_sigma), and Q = 0 on the A-V couplings (-B_sigma), so the
+// row class decides c.  k_factor_pq recovers {P, Q} from one operator's
+// equilibrated complex128 values (val = s_i s_j (P + c0 Q)); k_spmv_mf reads
+// the factored matrix once for a chunk of systems of different frequencies:
+// y_r = s_r (P + c_r Q) u_r with u_r = s_r x_r (k_scale_sys), s_r the
+// equilibration of system r's operator; 8 lanes per row, complex64.
+__global__ __launch_bounds__(kThreads) void k_factor_pq(int64_t n, int64_t ne, const int* __restrict__ rowptr,
+                                                        const int* __restrict__ col, const double2* __restrict__ val,
+                                                        const double* __restrict__ s, double omega,
+                                                        float2* __restrict__ pq) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double si = s[i];
+  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    const double d = 1.0 / (si * s[col[p]]);
+    const double re = val[p].x * d, im = val[p].y * d;
+    pq[p] = make_float2((float)re, (float)(i < ne ? -im / omega : im * omega));
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_sys(int64_t n, const float2* __restrict__ x, int64_t ld,
+                                                        const mf_sys* __restrict__ sys, float2* __restrict__ u,
+                                                        const int* __restrict__ active) {
+  const int z = blockIdx.z;
+  if (active && !active[z]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float f = (float)sys[z].s[i];
+  const float2 v = x[(int64_t)z * ld + i];
+  u[(int64_t)z * ld + i] = make_float2(v.x * f, v.y * f);
+}
+
+__global__ __launch_bounds__(kThreads) void k_spmv_mf(int64_t n, int64_t ne, const int* __restrict__ rowptr,
+                                                      const int* __restrict__ col, const float2* __restrict__ pq,
+                                                      int nrhs, int64_t ld, const float2* __restrict__ u,
+                                                      float2* __restrict__ y, const mf_sys* __restrict__ sys,
+                                                      const int* __restrict__ active) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+  const int lane = threadIdx.x % kLanes;
+  for (int c0 = 0; c0 < nrhs; c0 += kBatchChunk) {
+    const int cn = min(kBatchChunk, nrhs - c0);
+    bool on[kBatchChunk];
+    float2 ap[kBatchChunk], aq[kBatchChunk];
+#pragma unroll
+    for (int q = 0; q < kBatchChunk; ++q) {
+      on[q] = q < cn && (!active || active[c0 + q]);
+      ap[q] = aq[q] = make_float2(0.f, 0.f);
+    }
+    if (row < n) {
+      for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) {
+        const float2 v = pq[p];
+        const int c = col[p];
+#pragma unroll
+        for (int q = 0; q < kBatchChunk; ++q)
+          if (on[q]) {
+            const float2 x = u[(int64_t)(c0 + q) * ld + c];
+            ap[q].x = fmaf(v.x, x.x, ap[q].x);
+            ap[q].y = fmaf(v.x, x.y, ap[q].y);
+            aq[q].x = fmaf(v.y, x.x, aq[q].x);
+            aq[q].y = fmaf(v.y, x.y, aq[q].y);
+          }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kBatchChunk; ++q)
+      for (int o = kLanes / 2; o > 0; o >>= 1) {
+        ap[q].x += __shfl_xor(ap[q].x, o, kLanes);
+        ap[q].y += __shfl_xor(ap[q].y, o, kLanes);
+        aq[q].x += __shfl_xor(aq[q].x, o, kLanes);
+        aq[q].y += __shfl_xor(aq[q].y, o, kLanes);
+      }
+    if (row < n && lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kBatchChunk; ++q)
+        if (on[q]) {
+          const mf_sys& sq = sys[c0 + q];
+          const float w = row < ne ? sq.w_a : sq.w_v, f = (float)sq.s[row];
+          // (P u) + i w (Q u), then the row scaling
+          y[(int64_t)(c0 + q) * ld + row] =
+              make_float2((ap[q].x - w * aq[q].y) * f, (ap[q].y + w * aq[q].x) * f);
+        }
+    }
+  }
+}
+
 // out_r = (T) in_r
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_convert_b(int64_t n, const double2* __restrict__ in, int64_t istride,
@@ -2117,6 +2205,15 @@ void launch_face(int64_t nf, const double* xyz, const int* face, const int* face
                  const double* sig_reg, double omega, double2* fbuf, double* area3, hipStream_t st) {
   if (nf <= 0) return;
   k_face<<<blocks_for(nf), kThreads, 0, st>>>(nf, xyz, face, face_region, nu_reg, sig_reg, omega, fbuf, area3);
+}
+void launch_factor_pq(int64_t n, int64_t ne, const int* rowptr, const int* col, const double2* val, const double* s,
+                      double omega, float2* pq, hipStream_t st) {
+  k_factor_pq<<<blocks_for(n), kThreads, 0, st>>>(n, ne, rowptr, col, val, s, omega, pq);
+}
+void launch_spmv_mf(int64_t n, int64_t ne, const int* rowptr, const int* col, const float2* pq, int nrhs, int64_t ld,
+                    const float2* x, float2* u, float2* y, const mf_sys* sys, const int* active, hipStream_t st) {
+  k_scale_sys<<<dim3(blocks_for(n), 1, nrhs), kThreads, 0, st>>>(n, x, ld, sys, u, active);
+  k_spmv_mf<<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, ne, rowptr, col, pq, nrhs, ld, u, y, sys, active);
 }
 void launch_diag_scale(int64_t n, const double2* in, const double* s, int divide, double2* out, hipStream_t st) {
   k_diag_scale<<<blocks_for(n), kThreads, 0, st>>>(n, in, s, divide, out, 0, 0);

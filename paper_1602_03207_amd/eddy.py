@@ -50,7 +50,8 @@ EXPORTS = [
     "eddy_mesh_create", "eddy_mesh_create_ibc", "eddy_ibc_split", "eddy_mesh_destroy", "eddy_mesh_counts", "eddy_mesh_edges",
     "eddy_mesh_conductor_nodes", "eddy_mesh_blocks", "eddy_op_workspace_bytes", "eddy_op_create",
     "eddy_op_destroy", "eddy_op_assemble", "eddy_rhs_from_current", "eddy_solve_workspace_bytes",
-    "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched", "eddy_impedance", "eddy_delta_z_volume",
+    "eddy_solve", "eddy_solve_batched_workspace_bytes", "eddy_solve_batched",
+    "eddy_solve_multifreq_workspace_bytes", "eddy_solve_multifreq", "eddy_impedance", "eddy_delta_z_volume",
     "eddy_ect_signals", "eddy_edge_field", "eddy_spmv", "eddy_precond_apply", "eddy_export", "eddy_profile", "eddy_op_tuning",
     "eddy_mesh_subdomains", "eddy_gnn_static_features", "eddy_gnn_scratch_bytes", "eddy_gnn_pair",
     "eddy_gnn_forward", "eddy_gnn_train_step",
@@ -82,6 +83,8 @@ def _load():
         "eddy_solve": [VP, VP, VP, P(_Opts), VP, C.c_size_t, P(_Report), VP],
         "eddy_solve_batched_workspace_bytes": [VP, I32, P(_Opts), P(C.c_size_t)],
         "eddy_solve_batched": [VP, I32, VP, VP, P(_Opts), VP, C.c_size_t, P(_Report), VP],
+        "eddy_solve_multifreq_workspace_bytes": [P(VP), I32, I32, P(_Opts), P(C.c_size_t)],
+        "eddy_solve_multifreq": [P(VP), I32, I32, P(I32), VP, VP, P(_Opts), VP, C.c_size_t, P(_Report), VP],
         "eddy_impedance": [VP, I32, VP, I32, VP, P(D), P(D), VP],
         "eddy_delta_z_volume": [VP, I32, VP, VP, I32, VP, P(D), P(D), P(D), VP],
         "eddy_ect_signals": [I32, P(D), P(D), P(D), P(D), P(D)],
@@ -492,3 +495,30 @@ class Operator:
                                 out["val"].ctypes.data_as(C.POINTER(D)), _ptr(out["wrowptr"], I), _ptr(out["wcol"], I),
                                 _ptr(out["wval"], D), _ptr(out["d0"], D), _ptr(out["s"], D), _stream()), "eddy_export")
         return out
+
+
+def solve_multifreq(ops, B, op_of_rhs, tol=1e-10, restart=30, max_iter=5000, out=None, precision="mixed"):
+    """eddy_solve_multifreq: B complex128 device [nrhs, ndof]; system r belongs
+    to ops[op_of_rhs[r]] (nondecreasing).  Returns (X [nrhs, ndof], [SolveReport])."""
+    import torch
+    ops = list(ops)
+    ndof = ops[0].ndof
+    B = B.reshape(-1, ndof).contiguous()
+    nrhs = B.shape[0]
+    idx = np.ascontiguousarray(op_of_rhs, dtype=np.int32)
+    if idx.size != nrhs:
+        raise ValueError("op_of_rhs needs one entry per right-hand side")
+    handles = (C.c_void_p * len(ops))(*[o._h.value if isinstance(o._h, C.c_void_p) else o._h for o in ops])
+    opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1, "mixed16": 2}[precision])
+    nbytes = C.c_size_t()
+    _check(_lib.eddy_solve_multifreq_workspace_bytes(handles, len(ops), nrhs, C.byref(opts), C.byref(nbytes)),
+           "eddy_solve_multifreq_workspace_bytes")
+    buf, p = _aligned(nbytes.value, ops[0].device)
+    X = torch.empty_like(B) if out is None else out
+    reps = (_Report * nrhs)()
+    _check(_lib.eddy_solve_multifreq(handles, len(ops), nrhs, _ptr(idx, C.c_int32), _dev(B), _dev(X), C.byref(opts),
+                                     p, nbytes.value, reps, _stream()), "eddy_solve_multifreq")
+    del buf
+    return X, [SolveReport(r.iters, r.restarts, bool(r.converged), bool(r.breakdown), r.relres, r.est_relres,
+                           r.seconds, bool(r.gauge_in_operator), r.cg_iters, r.div_residual, r.precision_used,
+                           r.reorth_steps) for r in reps]
