@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scan", type=int, default=8,
                     help="also time a batched scan of this many probe positions (0 = skip)")
+    ap.add_argument("--multifreq", type=int, default=4,
+                    help="also time a batch over this many frequencies (100, 240, 400, 600 kHz) x --mf-positions "
+                         "probe positions with the frequency-factored matrix, against per-frequency batches (0 = skip)")
+    ap.add_argument("--mf-positions", type=int, default=2)
     ap.add_argument("--learned-tubes", type=int, default=4,
                     help="perturbed 258k-tet tubes the learned correction trains on (0 = skip)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed16", "all"], default="all",
@@ -312,6 +316,43 @@ def main():
                 "speedup_vs_single_headline": round(sec_per_solve / (st / args.scan), 3),
                 "Z11": [[z[0, 0].real, z[0, 0].imag] for z in sZ]}
 
+    mfreq = None
+    if args.multifreq and args.workload == "tube":
+        from synth import probe_currents, tube_materials
+        freqs = [1e5, 2.4e5, 4e5, 6e5][:args.multifreq]
+        ops_f = []
+        for f in freqs:
+            o2 = op if f == 1e5 else eddy.Operator(M, tau=tau, block_size=args.block,
+                                                   tau_precond=tau * args.tau_precond_factor)
+            o2.assemble(nu, sig, tube_materials(f)[2])
+            ops_f.append(o2)
+        zs = np.linspace(-2e-3, 2e-3, args.mf_positions)
+        P = len(zs)
+        Bm = torch.stack([ops_f[0].rhs_from_current(torch.from_numpy(np.ascontiguousarray(
+            probe_currents(m, float(z))[0])).cuda()) for _ in freqs for z in zs])
+        idx = [fi for fi in range(len(freqs)) for _ in zs]
+        kw = dict(tol=args.tol, restart=args.restart, max_iter=args.max_iter, precision=head)
+        eddy.solve_multifreq(ops_f, Bm, idx, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xm, mreps = eddy.solve_multifreq(ops_f, Bm, idx, **kw)
+        torch.cuda.synchronize()
+        t_mf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sreps_f = []
+        for fi, o2 in enumerate(ops_f):
+            _, r2 = o2.solve_batched(Bm[fi * P:(fi + 1) * P].clone(), **kw)
+            sreps_f += r2
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter() - t0
+        mfreq = {"freqs_hz": freqs, "positions_per_freq": P, "systems": len(idx),
+                 "s_per_system": round(t_mf / len(idx), 4), "s_per_system_per_frequency_batches": round(t_sep / len(idx), 4),
+                 "speedup_vs_per_frequency_batches": round(t_sep / t_mf, 3),
+                 "iters": [r.iters for r in mreps], "iters_per_frequency_batches": [r.iters for r in sreps_f],
+                 "converged": all(r.converged for r in mreps) and all(r.converged for r in sreps_f),
+                 "max_relres": max(r.relres for r in mreps)}
+        del ops_f, Xm, Bm
+
     learned_out = None
     if args.learned_tubes and args.workload == "tube":
         learned_out = learned_section(args, op, b, head)
@@ -357,6 +398,7 @@ def main():
                         "Z11": [runs["fp64"]["Z"][0, 0].real, runs["fp64"]["Z"][0, 0].imag],
                         "kernels": runs["fp64"]["kernels"]} if "fp64" in runs and head != "fp64" else None),
         "batched_scan": scan,
+        "multifreq_batch": mfreq,
         "learned": learned_out,
         "host_setup_s": round(host_setup, 2),
         "spmv_tuning": op.tuning(),
