@@ -885,8 +885,8 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
       launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);
       launch_dcgs_coef(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est,
                        learned ? W.Sall : nullptr, learned ? W.rhoall : nullptr, s);
-      launch_dcgs_update(n, (const VT*)I.V, ld, j, W.coef, vj, I.w, W.rpart, W.tnorm, s);
-      launch_scale_by_inv(n, (const T*)I.w, W.tnorm, I.V + (int64_t)(j + 1) * ld, s);
+      launch_dcgs_update(n, (const VT*)I.V, ld, j, W.coef, vj, I.w, W.rpart, (double*)nullptr, s);
+      launch_scale_by_partials(n, (const T*)I.w, W.rpart, W.tnorm, I.V + (int64_t)(j + 1) * ld, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
       ++it;
       const bool last = j == m - 1 || it >= opts->max_iter;

@@ -141,9 +141,14 @@ template <class VT, class T>
 void launch_dcgs_update_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const double2* coef,
                           int64_t cstride, VT* v, T* w, int64_t wstride, double* rpart, double* out_norm,
                           const int* active, int nrhs, hipStream_t st);
+// out_norm may be null: the norm is then left in rpart's kRedBlocks partial
+// sums for launch_scale_by_partials
 template <class VT, class T>
 void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double2* coef, VT* v, T* w, double* rpart,
                         double* out_norm, hipStream_t st);
+// v = w / ||w|| from the partial sums of ||w||^2; ||w|| into out_norm
+template <class Ti, class To>
+void launch_scale_by_partials(int64_t n, const Ti* w, const double* rpart, double* out_norm, To* v, hipStream_t st);
 // Hessenberg least squares on the device
 void launch_givens(int j, int m, const double2* h1, const double2* h2, const double* nrm, double2* H, double* cs,
                    double2* sn, double2* g, double beta, double bnorm, double* est, hipStream_t st);

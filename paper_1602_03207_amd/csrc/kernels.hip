@@ -705,8 +705,15 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* _
     const int* __restrict__ c = scol + p0 + l;
     const T* __restrict__ v = sval + p0 + l;
     T acc = zero2<T>();
+    // column loads, then gathers, unrolled as deep as occupancy allows
+    // (measured: complex64 8 deep, 7 waves per SIMD; complex128 4 deep)
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll 8
+      for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+    } else {
 #pragma unroll 4
-    for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+      for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+    }
     if (row >= 0) y[row] = b ? st2<T>(csub(b[row], ld2(acc))) : acc;
   }
 }
@@ -1035,6 +1042,48 @@ __global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const Ti* 
   if (i0 >= n) return;
   const double a = nrm[0];
   const double f = a > 0.0 ? 1.0 / a : 0.0;
+  if (vec && i0 + R <= n) {
+    constexpr int Gi = rows_of<Ti>::R, Go = rows_of<To>::R;
+    const double fr = f * basis_unscale<Ti>();
+    double2 x[R];
+#pragma unroll
+    for (int g = 0; g < R; g += Gi) ld_rows(w + i0 + g, x + g);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = make_double2(x[r].x * fr, x[r].y * fr);
+#pragma unroll
+    for (int g = 0; g < R; g += Go) st_rows(v + i0 + g, x + g);
+    return;
+  }
+  for (int r = 0; r < R && i0 + r < n; ++r) {
+    const double2 x = ld2(w[i0 + r]);
+    v[i0 + r] = st2<To>(make_double2(x.x * f, x.y * f));
+  }
+}
+
+// v = w / ||w|| with ||w||^2 the sum of the kRedBlocks partial sums rpart,
+// formed by every workgroup in k_norm2_final's order (so the same value
+// everywhere, equal to k_norm2_final's); workgroup 0 stores ||w|| in
+// out_norm.  Saves the dependent launch of k_norm2_final per Arnoldi step.
+template <class Ti, class To>
+__global__ __launch_bounds__(kThreads) void k_scale_by_partials(int64_t n, const Ti* __restrict__ w,
+                                                                const double* __restrict__ rpart,
+                                                                double* __restrict__ out_norm, To* __restrict__ v,
+                                                                int vec) {
+  constexpr int R = scale_rows<Ti, To>();
+  __shared__ double sh[4];
+  __shared__ double nrm_s;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) acc += rpart[b];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    nrm_s = sqrt(acc);
+    if (blockIdx.x == 0) out_norm[0] = nrm_s;
+  }
+  __syncthreads();
+  const double a = nrm_s;
+  const double f = a > 0.0 ? 1.0 / a : 0.0;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R;
+  if (i0 >= n) return;
   if (vec && i0 + R <= n) {
     constexpr int Gi = rows_of<Ti>::R, Go = rows_of<To>::R;
     const double fr = f * basis_unscale<Ti>();
@@ -1448,10 +1497,28 @@ __device__ void backsolve_body(int k, int m, const double2* __restrict__ H, cons
   }
 }
 
-__global__ void k_backsolve(int k, int m, const double2* __restrict__ H, const double2* __restrict__ g,
-                            double2* __restrict__ y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  backsolve_body(k, m, H, g, y);
+// the same with the triangle staged in LDS first (packed rows, loaded by
+// the whole workgroup), so the serial recurrence reads no global memory
+__global__ __launch_bounds__(64) void k_backsolve(int k, int m, const double2* __restrict__ H,
+                                                  const double2* __restrict__ g, double2* __restrict__ y) {
+  __shared__ double2 T[kMaxRestart * (kMaxRestart + 1) / 2];
+  __shared__ double2 gs[kMaxRestart], ys[kMaxRestart];
+  // row i of the triangle (columns i..k-1) starts at i k - i (i - 1) / 2
+  for (int i = 0; i < k; ++i)
+    for (int l = i + threadIdx.x; l < k; l += blockDim.x) T[i * k - i * (i - 1) / 2 + (l - i)] = H[i * m + l];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = g[i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    const double2* Ti = T + (i * k - i * (i - 1) / 2);
+    double2 acc = gs[i];
+    for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(Ti[l - i], ys[l]));
+    const double2 d = Ti[0];
+    const double den = d.x * d.x + d.y * d.y;
+    // a zero pivot (a direction the preconditioner annihilated) contributes nothing
+    ys[i] = den > 0.0 ? cmul(acc, make_double2(d.x / den, -d.y / den)) : make_double2(0.0, 0.0);
+    y[i] = ys[i];
+  }
 }
 
 __global__ void k_backsolve_b(const int* __restrict__ ks, int m, const double2* __restrict__ H,
@@ -1932,8 +1999,12 @@ void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, con
   k_block_apply<T, MT, RT><<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, r, z);
 }
 int mdot2_parts(int64_t n) {
-  const int64_t tiles = (n + 2 * kThreads - 1) / (2 * kThreads);     // tiles of the smallest row groups
-  return (int)(tiles < kDot2MaxBlocks ? (tiles > 0 ? tiles : 1) : kDot2MaxBlocks);
+  // tiles of the widest row groups (4 rows per thread); every workgroup gets
+  // the same number of tiles (the smaller groups split each tile in two)
+  const int64_t tiles = (n + 4 * kThreads - 1) / (4 * kThreads);
+  const int64_t per = (tiles + kDot2MaxBlocks - 1) / kDot2MaxBlocks;
+  const int64_t parts = per > 0 ? (tiles + per - 1) / per : 1;
+  return (int)(parts > 0 ? parts : 1);
 }
 int mdot_parts(int64_t n) { return (int)((n + 2 * kThreads - 1) / (2 * kThreads)); }
 template <class T>
@@ -2015,7 +2086,13 @@ void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double
                         double* out_norm, hipStream_t st) {
   k_dcgs_update<VT, T><<<kRedBlocks, kThreads, 0, st>>>(n, V, ldv, q, coef, v, w, rpart, 0, 0, 0, nullptr,
                                                         rows_aligned<VT>(V, v, w, ldv, 0, 0));
-  k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, nullptr, nullptr);
+  if (out_norm) k_norm2_final<<<1, kThreads, 0, st>>>(rpart, out_norm, nullptr, nullptr);
+}
+template <class Ti, class To>
+void launch_scale_by_partials(int64_t n, const Ti* w, const double* rpart, double* out_norm, To* v, hipStream_t st) {
+  constexpr int R = scale_rows<Ti, To>();
+  k_scale_by_partials<Ti, To><<<blocks_for((n + R - 1) / R), kThreads, 0, st>>>(n, w, rpart, out_norm, v,
+                                                                                 vec_ok(R, w, v, 0, 0));
 }
 template <class VT, class T>
 void launch_mdot2_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const VT* v, const T* w,
@@ -2142,6 +2219,12 @@ template void launch_dcgs_update<float2, float2>(int64_t, const float2*, int64_t
 template void launch_dcgs_update<hbasis, float2>(int64_t, const hbasis*, int64_t, int, const double2*, hbasis*,
                                                  float2*, double*, double*, hipStream_t);
 template void launch_scale_by_inv<float2, hbasis>(int64_t, const float2*, const double*, hbasis*, hipStream_t);
+template void launch_scale_by_partials<float2, hbasis>(int64_t, const float2*, const double*, double*, hbasis*,
+                                                       hipStream_t);
+template void launch_scale_by_partials<float2, float2>(int64_t, const float2*, const double*, double*, float2*,
+                                                       hipStream_t);
+template void launch_scale_by_partials<double2, double2>(int64_t, const double2*, const double*, double*, double2*,
+                                                         hipStream_t);
 template void launch_scale_host<double2, hbasis>(int64_t, const double2*, double, hbasis*, hipStream_t);
 template void launch_combine<hbasis, float2>(int64_t, const hbasis*, int64_t, int, const double2*, float2*,
                                              hipStream_t);
