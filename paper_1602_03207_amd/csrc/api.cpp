@@ -1205,7 +1205,8 @@ eddy_status run_batched(eddy_op* o, const Groups& G, BatchWs& B, const eddy_solv
       const int* ag = act ? act + g0 : nullptr;
       const T* minv = std::is_same<T, float2>::value ? (const T*)og->minv32 : (const T*)og->minv;
       if constexpr (std::is_same<RT, hbasis>::value) {
-        launch_block_apply_b(og->nb, og->blk_ptr, og->blk_dofs, og->minv16, gn, rstride, rg, ld, zg, ag, s);
+        // complex-half inverses times the complex-half basis: matrix cores
+        launch_block_apply_mfma(og->nb, og->blk_ptr, og->blk_dofs, og->minv16, gn, rstride, rg, ld, zg, ag, s);
       } else {
         bool done = false;
         if constexpr (std::is_same<T, float2>::value) {

@@ -84,6 +84,11 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st);
 template <class T, class MT, class RT>
 void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, int nrhs,
                           int64_t rstride, const RT* r, int64_t zstride, T* z, const int* active, hipStream_t st);
+// the same for complex-half inverses and inputs on the matrix cores (f16
+// MFMA, float32 sums); every inverse column past the block size must be zero
+void launch_block_apply_mfma(int64_t nb, const int* blk_ptr, const int* blk_dofs, const uint32_t* minv, int nrhs,
+                             int64_t rstride, const hbasis* r, int64_t zstride, float2* z, const int* active,
+                             hipStream_t st);
 template <class T>
 void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, int nrhs, int64_t ld, const T* x,
                    const T* b, T* y, const int* active, hipStream_t st);

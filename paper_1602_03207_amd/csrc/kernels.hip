@@ -442,8 +442,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_block_invert(
     }
   }
   __syncthreads();
+  // all 64 columns: those past sz are zero (the MFMA apply reads them)
   double2* out = minv + (int64_t)k * kMaxBlock * kMaxBlock;
-  for (int j = 0; j < sz; ++j) out[j * kMaxBlock + i] = A[j * kMaxBlock + i];
+  for (int j = 0; j < kMaxBlock; ++j) out[j * kMaxBlock + i] = A[j * kMaxBlock + i];
 }
 
 // rbuf[l*nt + t] = s_l J_t . |K|/4 (grad l_b - grad l_a)   (int J . w_l)
@@ -1575,6 +1576,102 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_b(int64_t nb, const in
   }
 }
 
+// Batched block-Jacobi apply on the matrix cores, for complex-half
+// inverses and complex-half (scaled) inputs: per 64-DOF block and chunk of 8
+// systems, Z = M R with M = Mr + i Mi (64 x 64) and R = Rr + i Ri (64 x 8)
+// is the real product [Zr Zi] = Mr [Rr Ri] + Mi [-Ri Rr] (64 x 64 times
+// 64 x 16), eight v_mfma_f32_16x16x16_f16 per 16-row tile.  Half x half
+// products are exact in float32 and the sums are float32, as in
+// k_block_apply_b; only the order of the sums differs.  One wavefront per
+// block, 4 blocks per workgroup; R is staged in LDS.  Fragment layout of
+// v_mfma_f32_16x16x16_f16: lane l supplies A(l % 16, 4 (l / 16) + u) and
+// B(4 (l / 16) + u, l % 16), u = 0..3, and receives D(4 (l / 16) + u, l % 16).
+// The inverses' columns past the block size are zero (k_block_invert).
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kThreads) void k_block_apply_mfma(int64_t nb, const int* __restrict__ blk_ptr,
+                                                               const int* __restrict__ blk_dofs,
+                                                               const uint32_t* __restrict__ minv, int nrhs,
+                                                               int64_t rstride, const hbasis* __restrict__ r,
+                                                               int64_t zstride, float2* __restrict__ z,
+                                                               const int* __restrict__ active) {
+  __shared__ uint32_t rl[4][kBatchChunk][kMaxBlock];
+  __shared__ int dl[4][kMaxBlock];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + w;
+  int b0 = 0, sz = 0;
+  if (k < nb) {
+    b0 = blk_ptr[k];
+    sz = blk_ptr[k + 1] - b0;
+  }
+  dl[w][l] = l < sz ? blk_dofs[b0 + l] : -1;
+  const uint32_t* Mk = minv + (k < nb ? k : 0) * kMaxBlock * kMaxBlock;
+  const int n = l & 15, q = n & 7, kq = (l >> 4) * 4;
+  const bool imag_col = n >= 8;
+  // the block's A fragments (16 KB per wavefront) are issued before the
+  // right-hand sides are gathered and stay in registers for every chunk
+  uint32_t mw[4][4][4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) mw[ks][t][u] = ld_stream(Mk + (ks * 16 + kq + u) * kMaxBlock + t * 16 + n);
+  for (int c0 = 0; c0 < nrhs; c0 += kBatchChunk) {
+    const int cn = min(kBatchChunk, nrhs - c0);
+    __syncthreads();   // dl written / previous chunk's rl consumed
+#pragma unroll
+    for (int s = 0; s < kBatchChunk; ++s) {
+      const int dof = dl[w][l];
+      const bool on = s < cn && dof >= 0 && (!active || active[c0 + s]);
+      rl[w][s][l] = on ? r[(int64_t)(c0 + s) * rstride + dof].b : 0u;
+    }
+    __syncthreads();
+    if (k >= nb) continue;
+    f4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (f4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int k0 = ks * 16;
+      h4_t b1, b2;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t x = rl[w][q][k0 + kq + u];
+        const _Float16 re = __builtin_bit_cast(_Float16, (unsigned short)(x & 0xffffu));
+        const _Float16 im = __builtin_bit_cast(_Float16, (unsigned short)(x >> 16));
+        b1[u] = imag_col ? im : re;
+        b2[u] = imag_col ? re : -im;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        h4_t ar, ai;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t m = mw[ks][t][u];
+          ar[u] = __builtin_bit_cast(_Float16, (unsigned short)(m & 0xffffu));
+          ai[u] = __builtin_bit_cast(_Float16, (unsigned short)(m >> 16));
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, b1, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(ai, b2, acc[t], 0, 0, 0);
+      }
+    }
+    // lane n < 8 holds the real parts of system n, lane n + 8 the imaginary
+    // parts: pair them, undo the inputs' 2^14 scale
+    constexpr float us = 1.0f / 16384.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float other = __shfl_xor(acc[t][u], 8, 64);
+        const int row = t * 16 + kq + u;
+        const int dof = dl[w][row];
+        if (!imag_col && q < cn && dof >= 0 && (!active || active[c0 + q]))
+          z[(int64_t)(c0 + q) * zstride + dof] = make_float2(acc[t][u] * us, other * us);
+      }
+  }
+}
+
 // y_r = M~ x_r (penalty-free operator), or y_r = b_r - M~ x_r if b; 8 lanes per row.
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_spmv_b(int64_t n, const int* __restrict__ rowptr,
@@ -2263,6 +2360,12 @@ template void launch_block_apply_b<float2, uint32_t, float2>(int64_t, const int*
 template void launch_block_apply_b<float2, uint32_t, hbasis>(int64_t, const int*, const int*, const uint32_t*, int,
                                                              int64_t, const hbasis*, int64_t, float2*, const int*,
                                                              hipStream_t);
+void launch_block_apply_mfma(int64_t nb, const int* blk_ptr, const int* blk_dofs, const uint32_t* minv, int nrhs,
+                             int64_t rstride, const hbasis* r, int64_t zstride, float2* z, const int* active,
+                             hipStream_t st) {
+  k_block_apply_mfma<<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, nrhs, rstride, r, zstride,
+                                                             z, active);
+}
 template void launch_scale_by_inv_b<double2, float2>(int64_t, const double2*, int64_t, const double*, float2*, int64_t,
                                                      const int*, int, hipStream_t);
 template void launch_scale_by_inv_b<double2, hbasis>(int64_t, const double2*, int64_t, const double*, hbasis*, int64_t,
