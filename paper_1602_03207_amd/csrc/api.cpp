@@ -1109,6 +1109,8 @@ struct BatchWs {
   // several frequencies: factored matrix, scaled SpMV input, per-system data
   float2 *pq = nullptr, *u = nullptr;
   mf_sys* sys = nullptr;
+  // precision 2: the block apply's output interleaved per chunk of 8 systems
+  float2* zI = nullptr;
 };
 
 // Systems of a batch grouped by operator: group g holds the systems
@@ -1168,6 +1170,7 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
   P.nrm = c.take<double>(8);
   P.xtmp = c.take<double2>(n);
   P.wtmp = c.take<double2>(n);
+  if (precision == 2) B->zI = c.take<float2>((int64_t)(nrhs + kBatchChunk - 1) / kBatchChunk * kBatchChunk * ld);
   if (multi) {
     B->pq = c.take<float2>(o->nnz);
     B->u = c.take<float2>((int64_t)nrhs * ld);
@@ -1205,8 +1208,11 @@ eddy_status run_batched(eddy_op* o, const Groups& G, BatchWs& B, const eddy_solv
       const int* ag = act ? act + g0 : nullptr;
       const T* minv = std::is_same<T, float2>::value ? (const T*)og->minv32 : (const T*)og->minv;
       if constexpr (std::is_same<RT, hbasis>::value) {
-        // complex-half inverses times the complex-half basis: matrix cores
-        launch_block_apply_mfma(og->nb, og->blk_ptr, og->blk_dofs, og->minv16, gn, rstride, rg, ld, zg, ag, s);
+        // complex-half inverses times the complex-half basis: matrix cores;
+        // with one operator the output goes interleaved to the SpMV
+        const bool il = ng == 1;
+        launch_block_apply_mfma(og->nb, og->blk_ptr, og->blk_dofs, og->minv16, gn, rstride, rg, ld, il ? B.zI : reinterpret_cast<float2*>(zg),
+                                ag, il ? 1 : 0, s);
       } else {
         bool done = false;
         if constexpr (std::is_same<T, float2>::value) {
@@ -1223,6 +1229,10 @@ eddy_status run_batched(eddy_op* o, const Groups& G, BatchWs& B, const eddy_solv
   // matrix for several
   auto inner_spmv = [&]() {
     if (ng == 1) {
+      if constexpr (std::is_same<VT, hbasis>::value) {
+        launch_spmv_b_il(n, o->rowptr, o->col, o->val32, nrhs, ld, B.zI, wT, B.run, s);
+        return;
+      }
       launch_spmv_b(n, o->rowptr, o->col, val, nrhs, ld, (const T*)zT, (const T*)nullptr, wT, B.run, s);
       return;
     }

@@ -86,9 +86,13 @@ void launch_block_apply_b(int64_t nb, const int* blk_ptr, const int* blk_dofs, c
                           int64_t rstride, const RT* r, int64_t zstride, T* z, const int* active, hipStream_t st);
 // the same for complex-half inverses and inputs on the matrix cores (f16
 // MFMA, float32 sums); every inverse column past the block size must be zero
+// (interleave: z per chunk of 8 systems as [row][8], the input of launch_spmv_b_il)
 void launch_block_apply_mfma(int64_t nb, const int* blk_ptr, const int* blk_dofs, const uint32_t* minv, int nrhs,
                              int64_t rstride, const hbasis* r, int64_t zstride, float2* z, const int* active,
-                             hipStream_t st);
+                             int interleave, hipStream_t st);
+// complex64 batched SpMV with an interleaved input (xil[((c0/8) ld + row) 8 + q])
+void launch_spmv_b_il(int64_t n, const int* rowptr, const int* col, const float2* val, int nrhs, int64_t ld,
+                      const float2* xil, float2* y, const int* active, hipStream_t st);
 template <class T>
 void launch_spmv_b(int64_t n, const int* rowptr, const int* col, const T* val, int nrhs, int64_t ld, const T* x,
                    const T* b, T* y, const int* active, hipStream_t st);

@@ -1594,7 +1594,7 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_mfma(int64_t nb, const
                                                                const uint32_t* __restrict__ minv, int nrhs,
                                                                int64_t rstride, const hbasis* __restrict__ r,
                                                                int64_t zstride, float2* __restrict__ z,
-                                                               const int* __restrict__ active) {
+                                                               const int* __restrict__ active, int interleave) {
   __shared__ uint32_t rl[4][kBatchChunk][kMaxBlock];
   __shared__ int dl[4][kMaxBlock];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -1666,8 +1666,12 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_mfma(int64_t nb, const
         const float other = __shfl_xor(acc[t][u], 8, 64);
         const int row = t * 16 + kq + u;
         const int dof = dl[w][row];
-        if (!imag_col && q < cn && dof >= 0 && (!active || active[c0 + q]))
-          z[(int64_t)(c0 + q) * zstride + dof] = make_float2(acc[t][u] * us, other * us);
+        if (!imag_col && q < cn && dof >= 0 && (!active || active[c0 + q])) {
+          // interleaved: the chunk's 8 systems side by side per row (see k_spmv_b_il)
+          const int64_t o = interleave ? ((int64_t)(c0 / kBatchChunk) * zstride + dof) * kBatchChunk + q
+                                       : (int64_t)(c0 + q) * zstride + dof;
+          z[o] = make_float2(acc[t][u] * us, other * us);
+        }
       }
   }
 }
@@ -1799,6 +1803,49 @@ __global__ __launch_bounds__(kThreads) void k_spmv_mf(int64_t n, int64_t ne, con
           y[(int64_t)(c0 + q) * ld + row] =
               make_float2((ap[q].x - w * aq[q].y) * f, (ap[q].y + w * aq[q].x) * f);
         }
+    }
+  }
+}
+
+// k_spmv_b for complex64 with the input interleaved per chunk of 8 systems:
+// x of system c0 + q at row c is xil[((c0 / 8) ld + c) 8 + q], so one
+// 64-byte load per matrix entry serves the whole chunk (the systems' own
+// vectors would be 8 separate gathers).  Output per system at stride ld.
+__global__ __launch_bounds__(kThreads) void k_spmv_b_il(int64_t n, const int* __restrict__ rowptr,
+                                                        const int* __restrict__ col, const float2* __restrict__ val,
+                                                        int nrhs, int64_t ld, const float2* __restrict__ xil,
+                                                        float2* __restrict__ y, const int* __restrict__ active) {
+  static_assert(kBatchChunk == 8, "four 16-byte loads per entry");
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+  const int lane = threadIdx.x % kLanes;
+  for (int c0 = 0; c0 < nrhs; c0 += kBatchChunk) {
+    const int cn = min(kBatchChunk, nrhs - c0);
+    const float4* __restrict__ xc = reinterpret_cast<const float4*>(xil + (int64_t)(c0 / kBatchChunk) * ld * kBatchChunk);
+    float2 acc[kBatchChunk];
+#pragma unroll
+    for (int q = 0; q < kBatchChunk; ++q) acc[q] = make_float2(0.f, 0.f);
+    if (row < n) {
+      for (int p = rowptr[row] + lane; p < rowptr[row + 1]; p += kLanes) {
+        const float2 v = val[p];
+        const float4* xp = xc + (int64_t)col[p] * (kBatchChunk / 2);
+        const float4 a[4] = {xp[0], xp[1], xp[2], xp[3]};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          acc[2 * h] = cfmaT(v, make_float2(a[h].x, a[h].y), acc[2 * h]);
+          acc[2 * h + 1] = cfmaT(v, make_float2(a[h].z, a[h].w), acc[2 * h + 1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kBatchChunk; ++q)
+      for (int o = kLanes / 2; o > 0; o >>= 1) {
+        acc[q].x += __shfl_xor(acc[q].x, o, kLanes);
+        acc[q].y += __shfl_xor(acc[q].y, o, kLanes);
+      }
+    if (row < n && lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kBatchChunk; ++q)
+        if (q < cn && (!active || active[c0 + q])) y[(int64_t)(c0 + q) * ld + row] = acc[q];
     }
   }
 }
@@ -2362,9 +2409,13 @@ template void launch_block_apply_b<float2, uint32_t, hbasis>(int64_t, const int*
                                                              hipStream_t);
 void launch_block_apply_mfma(int64_t nb, const int* blk_ptr, const int* blk_dofs, const uint32_t* minv, int nrhs,
                              int64_t rstride, const hbasis* r, int64_t zstride, float2* z, const int* active,
-                             hipStream_t st) {
+                             int interleave, hipStream_t st) {
   k_block_apply_mfma<<<blocks_for(nb, 4), kThreads, 0, st>>>(nb, blk_ptr, blk_dofs, minv, nrhs, rstride, r, zstride,
-                                                             z, active);
+                                                             z, active, interleave);
+}
+void launch_spmv_b_il(int64_t n, const int* rowptr, const int* col, const float2* val, int nrhs, int64_t ld,
+                      const float2* xil, float2* y, const int* active, hipStream_t st) {
+  k_spmv_b_il<<<blocks_for(n * kLanes), kThreads, 0, st>>>(n, rowptr, col, val, nrhs, ld, xil, y, active);
 }
 template void launch_scale_by_inv_b<double2, float2>(int64_t, const double2*, int64_t, const double*, float2*, int64_t,
                                                      const int*, int, hipStream_t);
