@@ -199,8 +199,8 @@ def cpu_baseline(args, gpu_iters):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is described "
-              f"in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): right-hand sides shard across GPUs "
+              f"without communication, but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
