@@ -288,6 +288,26 @@ def test_batched_solve_matches_single_solves(precision):
         assert np.linalg.norm(X[r].cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "mixed16"])
+def test_batched_solve_with_two_chunks(precision):
+    """10 systems: the batched kernels take 8 systems per pass, so the second
+    pass (systems 8, 9; the interleaved SpMV input and the matrix-core block
+    apply at mixed16) is covered too."""
+    from oracle.solve import direct
+    from oracle.post import remove_v_mean
+    m, s, op, _ = case("c1")
+    Js = [cube_current(m, seed) for seed in range(10)]
+    B = torch.stack([op.rhs_from_current(torch.from_numpy(J).cuda()) for J in Js])
+    X, reps = op.solve_batched(B, tol=1e-11, restart=30, max_iter=3000, precision=precision)
+    for r in (0, 7, 8, 9):
+        x1, rep1 = op.solve(B[r].clone(), tol=1e-11, restart=30, max_iter=3000, precision=precision)
+        assert reps[r].converged and reps[r].relres <= 1e-11
+        assert abs(reps[r].iters - rep1.iters) <= 1, (r, reps[r].iters, rep1.iters)
+        assert torch.linalg.norm(X[r] - x1).item() <= 1e-9 * torch.linalg.norm(x1).item()
+        xo = remove_v_mean(s, direct(s, s.rhs(Js[r])))
+        assert np.linalg.norm(X[r].cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
 def test_batched_solve_rejects_non_solenoidal_and_handles_zero_rhs():
     from paper_1602_03207_amd import eddy
     m, s, op, J = case("c1")
