@@ -62,6 +62,8 @@ def parse():
                     help="also time a batch over this many frequencies (100, 240, 400, 600 kHz) x --mf-positions "
                          "probe positions with the frequency-factored matrix, against per-frequency batches (0 = skip)")
     ap.add_argument("--mf-positions", type=int, default=2)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="also time the headline solve with its Arnoldi chunks as captured HIP graphs (0 = skip)")
     ap.add_argument("--learned-tubes", type=int, default=4,
                     help="perturbed 258k-tet tubes the learned correction trains on (0 = skip)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed16", "all"], default="all",
@@ -219,19 +221,19 @@ def main():
     b = torch.empty((2, op.ndof), dtype=torch.complex128, device="cuda")
     x = torch.empty(op.ndof, dtype=torch.complex128, device="cuda")
 
-    def make_step(prec):
+    def make_step(prec, graph=False):
         def step():
             op.assemble(nu, sig, omega)
             op.rhs_from_current(J1d, out=b[0])
             op.rhs_from_current(J2d, out=b[1])
             _, rep = op.solve(b[0], tol=args.tol, restart=args.restart, max_iter=args.max_iter, out=x,
-                              precision=prec)
+                              precision=prec, graph=graph)
             Z = op.impedance(x[None], b, [1.0, 1.0])
             return rep, Z
         return step
 
-    def timed(prec):
-        step = make_step(prec)
+    def timed(prec, graph=False):
+        step = make_step(prec, graph)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -261,6 +263,7 @@ def main():
 
     head = "mixed16" if args.precision == "all" else args.precision
     runs = {head: timed(head)}
+    graph_run = timed(head, graph=True) if args.graph else None
     if args.precision == "all":
         runs["mixed"] = timed("mixed")
         runs["fp64"] = timed("fp64")
@@ -397,6 +400,9 @@ def main():
                         "speedup_of_headline": round(runs["fp64"]["sec"] / sec_per_solve, 3),
                         "Z11": [runs["fp64"]["Z"][0, 0].real, runs["fp64"]["Z"][0, 0].imag],
                         "kernels": runs["fp64"]["kernels"]} if "fp64" in runs and head != "fp64" else None),
+        "graph": ({"s_per_solve": round(graph_run["sec"], 4), "iters": graph_run["rep"].iters,
+                   "speedup_vs_eager": round(sec_per_solve / graph_run["sec"], 3),
+                   "same_iterations": graph_run["rep"].iters == rep.iters} if graph_run else None),
         "batched_scan": scan,
         "multifreq_batch": mfreq,
         "learned": learned_out,

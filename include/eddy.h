@@ -83,6 +83,12 @@ typedef struct {
                            /* parameters (EDDY_GNN_PARAMS floats) of the learned    */
                            /* coarse correction, applied inside flexible GMRES     */
                            /* with fallback (see eddy_gnn_* below)                 */
+  int32_t graph;       /* 1: run the Arnoldi steps between two reads of the        */
+                       /* residual estimates (8 steps) as captured HIP graphs,     */
+                       /* kept per operator for the last solve workspace,         */
+                       /* precision, restart length and operator mode (a new one   */
+                       /* recaptures).  Not used in learned or profiled cycles.    */
+                       /* Results are identical to graph = 0.                      */
 } eddy_solve_opts;
 
 typedef struct {

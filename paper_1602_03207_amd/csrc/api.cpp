@@ -107,9 +107,21 @@ struct eddy_op {
   hipEvent_t ev[5 * kCheckEvery] = {};   // per-iteration event ring of one check window
   double prof_ms[5] = {0, 0, 0, 0, 0};
   int64_t prof_n[5] = {0, 0, 0, 0, 0};
+  // captured Arnoldi chunks (kCheckEvery steps each) of the plain solve, for
+  // one solve workspace, precision, restart length and operator mode
+  std::vector<hipGraphExec_t> gexec;
+  const void* g_ws = nullptr;
+  int g_prec = -1, g_m = 0, g_gauge = -1;
+  void drop_graphs() {
+    for (auto& g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+    gexec.clear();
+    g_ws = nullptr;
+  }
   ~eddy_op() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    drop_graphs();
   }
 };
 
@@ -716,6 +728,7 @@ eddy_status check_opts(const eddy_solve_opts* p) {
     set_error("precision must be 0 (fp64), 1 (mixed) or 2 (mixed, half-precision block inverses)");
     return EDDY_ERR_ARG;
   }
+  if (p->graph != 0 && p->graph != 1) { set_error("graph must be 0 or 1"); return EDDY_ERR_ARG; }
   return EDDY_OK;
 }
 }  // namespace
@@ -821,6 +834,34 @@ void inner_block_apply(const eddy_op* o, const Inner<T, VT>& I, const RT* r, T* 
 
 // Restarted right-preconditioned GMRES(m) with CGS2.  x~ (W.xt) starts at
 // zero, b~ = W.bt with ||b~|| = bnorm.  Returns with W.xt updated.
+// The graph of Arnoldi steps j0 .. j0 + kCheckEvery - 1, captured from step
+// on first use.  A capture or instantiation that fails turns graphs off for
+// the solve and returns null (nothing was executed: the caller runs the steps).
+template <class F>
+hipGraphExec_t graph_chunk(eddy_op* o, int j0, F& step, hipStream_t s, bool& use_graph) {
+  const size_t idx = (size_t)(j0 / kCheckEvery);
+  if (o->gexec.size() <= idx) o->gexec.resize(idx + 1, nullptr);
+  if (o->gexec[idx]) return o->gexec[idx];
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    use_graph = false;
+    return nullptr;
+  }
+  for (int j = j0; j < j0 + kCheckEvery; ++j) step(j);
+  hipError_t e = hipStreamEndCapture(s, &g);
+  hipGraphExec_t x = nullptr;
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess || !x) {
+    (void)hipGetLastError();
+    use_graph = false;
+    return nullptr;
+  }
+  o->gexec[idx] = x;
+  return x;
+}
+
 template <class T, class VT>
 eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_opts* opts, bool gauge_op,
                       double bnorm, int& it, eddy_solve_report& R, hipStream_t s) {
@@ -847,6 +888,15 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
   // than 25% worse (in log reduction) than the plain mean returns the solve
   // to plain block-Jacobi for good.
   const float* theta = opts->gnn_theta;
+  bool use_graph = opts->graph != 0 && !o->profile;
+  if (use_graph && (o->g_ws != (const void*)W.tnorm || o->g_prec != opts->precision || o->g_m != m ||
+                    o->g_gauge != (int)gauge_op)) {
+    o->drop_graphs();
+    o->g_ws = W.tnorm;
+    o->g_prec = opts->precision;
+    o->g_m = m;
+    o->g_gauge = (int)gauge_op;
+  }
   int cyc = 0, n_plain = 0, n_learn = 0;
   double lf_plain = 0.0, lf_learn = 0.0;
   bool fell_back = false;
@@ -856,9 +906,13 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
     // pending vector v_0 = r / beta; the DCGS2 step j finishes v_j and
     // projects the next direction once (see k_dcgs_coef)
     launch_scale_host(n, r, 1.0 / beta, I.V, s);
+    launch_set2(beta, bnorm, W.tnorm + 2, s);
     int k = 0, jstart = 0;     // jstart: first estimate index not yet checked
     bool stop = false;
-    for (int j = 0; j < m; ++j) {
+    // one Arnoldi step (every launch on s; beta and ||b|| from the device
+    // copies set at the cycle start, so a captured chunk of steps replays
+    // unchanged in later cycles and solves)
+    auto step = [&](int j) {
       VT* vj = I.V + (int64_t)j * ld;
       hipEvent_t* ev = o->ev + 5 * ((j % kCheckEvery));
       T* zj = learned ? I.Z + (int64_t)j * ld : I.z;
@@ -883,12 +937,28 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
       if (o->profile) (void)hipEventRecord(ev[3], s);
       launch_mdot2(n, (const VT*)I.V, ld, j, (const VT*)vj, (const T*)I.w, W.part, s);
       launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);
-      launch_dcgs_coef(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, beta, bnorm, W.est,
-                       learned ? W.Sall : nullptr, learned ? W.rhoall : nullptr, s);
+      launch_dcgs_coef_dev(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, W.tnorm + 2,
+                           W.tnorm + 3, W.est, learned ? W.Sall : nullptr, learned ? W.rhoall : nullptr, s);
       launch_dcgs_update(n, (const VT*)I.V, ld, j, W.coef, vj, I.w, W.rpart, (double*)nullptr, s);
       launch_scale_by_partials(n, (const T*)I.w, W.rpart, W.tnorm, I.V + (int64_t)(j + 1) * ld, s);
       if (o->profile) (void)hipEventRecord(ev[4], s);
-      ++it;
+    };
+    for (int j = 0; j < m; ++j) {
+      // kCheckEvery steps between two reads of the estimates: one captured
+      // graph when enabled (never in learned or profiled cycles, never past
+      // max_iter); a capture that fails runs the steps directly
+      hipGraphExec_t gx = nullptr;
+      if (use_graph && !learned && j % kCheckEvery == 0 && j + kCheckEvery <= m &&
+          it + kCheckEvery <= opts->max_iter)
+        gx = graph_chunk(o, j, step, s, use_graph);
+      if (gx) {
+        HIP_TRY(hipGraphLaunch(gx, s));
+        it += kCheckEvery;
+        j += kCheckEvery - 1;
+      } else {
+        step(j);
+        ++it;
+      }
       const bool last = j == m - 1 || it >= opts->max_iter;
       const bool check = last || (j + 1) % kCheckEvery == 0;
       if (!check) continue;

@@ -137,6 +137,12 @@ void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const do
                       double2* H, double* cs, double2* sn, double2* g, double beta, double bnorm, double* est,
                       double2* Sall, double* rhoall, hipStream_t st);
 void launch_flex_coeffs(int k, int m, const double2* Sall, const double* rhoall, double2* y, hipStream_t st);
+// the same with beta and ||b|| read from device memory (a captured step
+// stays valid across cycles), and the two-value store that sets them
+void launch_dcgs_coef_dev(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
+                          double2* H, double* cs, double2* sn, double2* g, const double* beta, const double* bnorm,
+                          double* est, double2* Sall, double* rhoall, hipStream_t st);
+void launch_set2(double a, double b, double* out, hipStream_t st);
 // batched forms (system z: V at z * vstride, w at z * wstride, partial at
 // z * pstride, dots and coef at z * dstride, Hessenberg data at the strides
 // of launch_givens_b; beta, bnorm, tnorm per system; active masks systems)

@@ -2208,6 +2208,19 @@ void launch_dcgs_coef(int j, int m, const double2* dots, double2* Hraw, const do
   k_dcgs_coef<<<1, 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, beta, bnorm, est, Sall, rhoall,
                                 nullptr, nullptr, 0, nullptr);
 }
+void launch_dcgs_coef_dev(int j, int m, const double2* dots, double2* Hraw, const double* tnorm, double2* coef,
+                          double2* H, double* cs, double2* sn, double2* g, const double* beta, const double* bnorm,
+                          double* est, double2* Sall, double* rhoall, hipStream_t st) {
+  k_dcgs_coef<<<1, 64, 0, st>>>(j, m, dots, Hraw, tnorm, coef, H, cs, sn, g, 0.0, 0.0, est, Sall, rhoall, beta,
+                                bnorm, 0, nullptr);
+}
+__global__ void k_set2(double a, double b, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+void launch_set2(double a, double b, double* out, hipStream_t st) { k_set2<<<1, 64, 0, st>>>(a, b, out); }
 // Flexible cycles: the basis vector q_j = (v_j - sum_{i<j} s_i^(j) q_i) / rho_j
 // was finished after z_j = B_j v_j was formed, so the columns matching the
 // Hessenberg matrix are Zt_j = (Z_j - sum_{i<j} s_i^(j) Zt_i) / rho_j.  Turn

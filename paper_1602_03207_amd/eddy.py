@@ -28,7 +28,7 @@ class _Params(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int32),
-                ("gnn_theta", C.c_void_p)]
+                ("gnn_theta", C.c_void_p), ("graph", C.c_int32)]
 
 
 class _Tuning(C.Structure):
@@ -341,16 +341,18 @@ class Operator:
         _check(_lib.eddy_rhs_from_current(self._h, _dev(J), _dev(b), _stream()), "eddy_rhs_from_current")
         return b
 
-    def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64", gnn_theta=None):
+    def solve(self, b, tol=1e-10, restart=30, max_iter=5000, out=None, precision="fp64", gnn_theta=None,
+              graph=False):
         """precision: "fp64", "mixed" (complex64 Krylov process, FP64 outer residual), or
         "mixed16" (as mixed, with the block-Jacobi inverses and the Krylov basis in complex half).
         gnn_theta: float32 device tensor of EDDY_GNN_PARAMS network parameters
-        (the learned coarse correction with fallback), or None."""
+        (the learned coarse correction with fallback), or None.  graph: run the
+        Arnoldi steps between residual checks as captured HIP graphs."""
         if gnn_theta is not None:
             assert gnn_theta.dtype.is_floating_point and gnn_theta.element_size() == 4 and gnn_theta.is_contiguous()
             assert gnn_theta.numel() == GNN_PARAMS
         opts = _Opts(tol, restart, max_iter, {"fp64": 0, "mixed": 1, "mixed16": 2}[precision],
-                     None if gnn_theta is None else gnn_theta.data_ptr())
+                     None if gnn_theta is None else gnn_theta.data_ptr(), 1 if graph else 0)
         nbytes = C.c_size_t()
         _check(_lib.eddy_solve_workspace_bytes(self._h, C.byref(opts), C.byref(nbytes)), "eddy_solve_workspace_bytes")
         if self._solve_ws is None or self._solve_ws[2] < nbytes.value:

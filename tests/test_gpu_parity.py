@@ -288,6 +288,24 @@ def test_batched_solve_matches_single_solves(precision):
         assert np.linalg.norm(X[r].cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("name,precision", [("c1", "fp64"), ("c1", "mixed16"), ("tube", "mixed16")])
+def test_graph_solve_equals_eager(name, precision):
+    """Captured Arnoldi chunks replay exactly the eager launches: the same
+    iterations and bitwise the same solution, over three solves that reuse
+    the graphs with eager work in between, and after a precision change
+    (the same operator: the graphs are captured again)."""
+    m, s, op, J = case(name)
+    b = op.rhs_from_current(torch.from_numpy(np.ascontiguousarray(J)).cuda())
+    kw = dict(tol=1e-10 if name == "c1" else 1e-8, restart=48, max_iter=20000, precision=precision)
+    x0, r0 = op.solve(b, **kw)
+    assert r0.converged
+    for k in range(3):
+        xg, rg = op.solve(b, graph=True, **kw)
+        assert rg.converged and rg.iters == r0.iters and torch.equal(xg, x0), (k, rg.iters, r0.iters)
+        op.spmv(xg)
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("precision", ["mixed", "mixed16"])
 def test_batched_solve_with_two_chunks(precision):
     """10 systems: the batched kernels take 8 systems per pass, so the second
