@@ -87,8 +87,8 @@ typedef struct {
                        /* residual estimates (8 steps) as captured HIP graphs,     */
                        /* kept per operator for the last solve workspace,         */
                        /* precision, restart length and operator mode (a new one   */
-                       /* recaptures).  Not used in learned or profiled cycles.    */
-                       /* Results are identical to graph = 0.                      */
+                       /* recaptures).  eddy_solve only; not used in learned or    */
+                       /* profiled cycles.  Results are identical to graph = 0.    */
 } eddy_solve_opts;
 
 typedef struct {
