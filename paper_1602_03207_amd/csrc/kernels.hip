@@ -425,7 +425,21 @@ __global__ __launch_bounds__(kMaxBlock) void k_block_invert(
     if (i < sz && i != kk) {
       const double2 f = A[kk * kMaxBlock + i];
       A[kk * kMaxBlock + i] = make_double2(0.0, 0.0);
-      for (int j = 0; j < sz; ++j) {
+      // eight columns per round, all loads before the stores: the compiler
+      // cannot tell that row kk (read) and row i (written) never alias, and
+      // one dependent LDS round trip per column left the update latency-bound
+      int j = 0;
+      for (; j + 8 <= sz; j += 8) {
+        double2 rk[8], av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          rk[u] = A[(j + u) * kMaxBlock + kk];
+          av[u] = A[(j + u) * kMaxBlock + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) A[(j + u) * kMaxBlock + i] = csub(av[u], cmul(f, rk[u]));
+      }
+      for (; j < sz; ++j) {
         const double2 rk = A[j * kMaxBlock + kk];
         A[j * kMaxBlock + i] = csub(A[j * kMaxBlock + i], cmul(f, rk));
       }
