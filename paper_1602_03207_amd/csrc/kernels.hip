@@ -345,11 +345,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_block_gauge(const int* __restrict
   double* out = gscr + (int64_t)k * kMaxBlock * kMaxBlock;
   for (int j = 0; j < sz; ++j) {
     const int cj = wc[j];
+    // the node lists of W's rows are sorted and unique: a merge visits the
+    // shared nodes in ascending order (the order of a double loop over q)
     double acc = 0.0;
-    for (int q = 0; q < cnt; ++q) {
-      const int nq = wn[i][q];
-      for (int u = 0; u < cj; ++u)
-        if (wn[j][u] == nq) acc += wd[i][q] * wv[j][u];
+    int q = 0, u = 0;
+    while (q < cnt && u < cj) {
+      const int nq = wn[i][q], nu = wn[j][u];
+      if (nq == nu) acc += wd[i][q++] * wv[j][u++];
+      else if (nq < nu) ++q;
+      else ++u;
     }
     out[j * kMaxBlock + i] = acc;
   }
