@@ -377,7 +377,9 @@ eddy_status eddy_export(const eddy_op* op, int32_t* rowptr, int32_t* col, eddy_c
                         eddy_stream stream);
 
 /* Per-kernel-class timing of the GMRES loop, measured with HIP events on the
- * solve's stream and read at the loop's per-iteration synchronisation.
+ * solve's stream and read at the loop's periodic synchronisation.  The
+ * events bracket one Arnoldi step in eight (a different step of each group
+ * of eight), so the counts are about an eighth of the iterations.
  * Classes: 0 block-Jacobi apply, 1 gauge product W~^T x, 2 SpMV
  * (+ W~ t), 3 CGS2 orthogonalisation + normalisation.  Returns (host) the
  * accumulated milliseconds ms[4] and launch counts counts[4] since the

@@ -908,6 +908,10 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
     launch_scale_host(n, r, 1.0 / beta, I.V, s);
     launch_set2(beta, bnorm, W.tnorm + 2, s);
     int k = 0, jstart = 0;     // jstart: first estimate index not yet checked
+    // timing events bracket one step in kCheckEvery, at a position that
+    // rotates from chunk to chunk (each event record costs a few
+    // microseconds of idle GPU between the kernels it separates)
+    auto profiled = [&](int j) { return o->profile && j % kCheckEvery == (j / kCheckEvery) % kCheckEvery; };
     bool stop = false;
     // one Arnoldi step (every launch on s; beta and ||b|| from the device
     // copies set at the cycle start, so a captured chunk of steps replays
@@ -915,8 +919,9 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
     auto step = [&](int j) {
       VT* vj = I.V + (int64_t)j * ld;
       hipEvent_t* ev = o->ev + 5 * ((j % kCheckEvery));
+      const bool prof = profiled(j);
       T* zj = learned ? I.Z + (int64_t)j * ld : I.z;
-      if (o->profile) (void)hipEventRecord(ev[0], s);
+      if (prof) (void)hipEventRecord(ev[0], s);
       inner_block_apply(o, I, (const VT*)vj, zj, s);
       if constexpr (std::is_same<T, VT>::value) {
         if (learned) {   // z_j += sum_p c_p (z_j on subdomain p), c from the network
@@ -927,21 +932,21 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
           launch_gnn_scale(o->blk_dofs, o->sub_ptr, o->gnn_Y, zj, s);
         }
       }
-      if (o->profile) (void)hipEventRecord(ev[1], s);
+      if (prof) (void)hipEventRecord(ev[1], s);
       if (gauge_op) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, (const double2*)zj, o->tvec, s);
-      if (o->profile) (void)hipEventRecord(ev[2], s);
+      if (prof) (void)hipEventRecord(ev[2], s);
       launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, I.sval, o->ne, gauge_op ? o->wrowptr : nullptr,
                   o->wcol, o->wval, o->tvec, (const T*)zj, nullptr, I.w, s,
                   std::is_same<T, float2>::value ? o->tune.spmv_grid_c64 : o->tune.spmv_grid_c128,
                   std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128, o->xcd_groups);
-      if (o->profile) (void)hipEventRecord(ev[3], s);
+      if (prof) (void)hipEventRecord(ev[3], s);
       launch_mdot2(n, (const VT*)I.V, ld, j, (const VT*)vj, (const T*)I.w, W.part, s);
       launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);
       launch_dcgs_coef_dev(j, m, W.dots, W.Hraw, W.tnorm, W.coef, W.Hd, W.csd, W.snd, W.gd, W.tnorm + 2,
                            W.tnorm + 3, W.est, learned ? W.Sall : nullptr, learned ? W.rhoall : nullptr, s);
       launch_dcgs_update(n, (const VT*)I.V, ld, j, W.coef, vj, I.w, W.rpart, (double*)nullptr, s);
       launch_scale_by_partials(n, (const T*)I.w, W.rpart, W.tnorm, I.V + (int64_t)(j + 1) * ld, s);
-      if (o->profile) (void)hipEventRecord(ev[4], s);
+      if (prof) (void)hipEventRecord(ev[4], s);
     };
     for (int j = 0; j < m; ++j) {
       // kCheckEvery steps between two reads of the estimates: one captured
@@ -977,7 +982,7 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
       if (o->profile) {
         const int j0 = j + 1 - ((j % kCheckEvery) + 1);
         for (int jj = j0; jj <= j; ++jj)
-          for (int c = 0; c < 4; ++c) {
+          for (int c = 0; c < 4 && profiled(jj); ++c) {
             float ms = 0;
             hipEvent_t* e = o->ev + 5 * (jj % kCheckEvery);
             if ((c != 1 || gauge_op) && hipEventElapsedTime(&ms, e[c], e[c + 1]) == hipSuccess) {

@@ -306,6 +306,28 @@ def test_graph_solve_equals_eager(name, precision):
         torch.cuda.synchronize()
 
 
+def test_profiled_solve_equals_plain_and_samples_one_step_in_eight():
+    """The timing events change no result, and they bracket one Arnoldi step
+    in eight (step 0 of every cycle among them): between one launch per
+    cycle and one per eight iterations plus two per cycle."""
+    m, s, op, J = case("c1")
+    b = op.rhs_from_current(torch.from_numpy(np.ascontiguousarray(J)).cuda())
+    kw = dict(tol=1e-10, restart=48, max_iter=20000, precision="mixed16")
+    x0, r0 = op.solve(b, **kw)
+    op.profile(True)
+    x1, r1 = op.solve(b, **kw)
+    prof = op.profile(False)
+    assert r1.iters == r0.iters and torch.equal(x1, x0)
+    cycles = r1.restarts + 1
+    for name in ("block_apply", "spmv", "cgs2"):
+        ms, cnt = prof[name]
+        print(f"{name}: {cnt} timed launches of {r1.iters} iterations, {cycles} cycles, {ms:.3f} ms")
+        assert cycles <= cnt <= r1.iters / 8 + 2 * cycles and ms > 0.0
+    if not r1.gauge_in_operator:
+        assert prof["gauge_wt"][1] == 0
+    assert op.profile(False)["spmv"] == (0.0, 0)
+
+
 @pytest.mark.parametrize("precision", ["mixed", "mixed16"])
 def test_batched_solve_with_two_chunks(precision):
     """10 systems: the batched kernels take 8 systems per pass, so the second
