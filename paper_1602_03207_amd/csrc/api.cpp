@@ -73,6 +73,8 @@ struct eddy_op {
   int *d0ptr, *d0list, *lcptr, *lclist, *rptr, *rlist;
   int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
   int *sell_ptr, *sell_row, *sell_col, *sell_src;
+  int* sell_cplx;                  // per slice: 1 complex64 values, 0 real (4-byte values)
+  std::vector<int64_t> sell_nz_h;  // per slice: stored nonzeros (padding excluded)
   int *lrowptr, *lcol;          // L = W^T G pattern (Coulomb projection)
   int* xcd_groups;              // SpMV schedule 1: group ranges of equal stored entries per XCD
   int64_t nnzl;
@@ -173,6 +175,7 @@ size_t carve_op(eddy_op* o, T* base, const eddy_mesh* m) {
   o->sell_src = c.take<int>(nsell);
   o->sval = c.take<double2>(nsell);
   o->sval32 = c.take<float2>(nsell);
+  o->sell_cplx = c.take<int>(ns);
   o->xcd_groups = c.take<int>(16);
   o->lrowptr = c.take<int>(m->nv + 1);
   o->lcol = c.take<int>((int64_t)m->lcol.size());
@@ -275,11 +278,11 @@ eddy_status tune_spmv(eddy_op* o, const T* sval, T* x, T* y, int* best_grid, int
     for (int g : caps) {
       if (g >= full) continue;
       launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, sval, o->ne, nullptr, nullptr, nullptr, nullptr, x,
-                  nullptr, y, s, g, sch, o->xcd_groups);
+                  nullptr, y, s, g, sch, o->xcd_groups, o->sell_cplx);
       (void)hipEventRecord(e0, s);
       for (int r = 0; r < reps; ++r)
         launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, sval, o->ne, nullptr, nullptr, nullptr, nullptr,
-                    x, nullptr, y, s, g, sch, o->xcd_groups);
+                    x, nullptr, y, s, g, sch, o->xcd_groups, o->sell_cplx);
       (void)hipEventRecord(e1, s);
       float ms = 0;
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -475,6 +478,14 @@ eddy_status eddy_op_create(const eddy_mesh* mc, const eddy_params* p, void* dev_
   UP(o->sell_ptr, m->sell_ptr); UP(o->sell_row, m->sell_row); UP(o->sell_col, m->sell_col);
   UP(o->sell_src, m->sell_src); UP(o->lrowptr, m->lrowptr); UP(o->lcol, m->lcol);
   {
+    const int64_t ns = (int64_t)m->sell_ptr.size() - 1;
+    o->sell_nz_h.assign(ns, 0);
+    for (int64_t q = 0; q < ns * kSellC; ++q) {
+      const int32_t r = m->sell_row[q];
+      if (r >= 0) o->sell_nz_h[q / kSellC] += m->rowptr[r + 1] - m->rowptr[r];
+    }
+  }
+  {
     // groups of 4 slices; XCD k starts at the first group whose entries reach k/8 of the total
     const int64_t ns = (int64_t)m->sell_ptr.size() - 1, ng = (ns + 3) / 4;
     const double tot = (double)m->sell_ptr[ns];
@@ -556,7 +567,7 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
   launch_to_c64(o->nnz, o->val, o->val32, s);
   launch_to_c64(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv32, s);
   launch_to_c16(o->nb * kMaxBlock * kMaxBlock, o->minv, o->minv16, s);
-  launch_sell_gather(o->nsell, o->sell_src, o->val, o->sval, o->sval32, s);
+  launch_sell_gather(o->nsell, o->ns, o->sell_ptr, o->sell_src, o->val, o->sval, o->sval32, o->sell_cplx, s);
   HIP_TRY(hipGetLastError());
   int stat = 0;
   HIP_TRY(hipMemcpyAsync(&stat, o->status, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -596,6 +607,12 @@ eddy_status eddy_op_assemble(eddy_op* o, const double* nu, const double* sigma, 
       ts = tune_spmv<float2>(o, o->sval32, (float2*)o->tmp1, (float2*)o->tmp2, &t.spmv_grid_c64, &t.spmv_sched_c64,
                              &t.spmv_us_c64, t.spmv_us_sched_c64, s);
     if (ts != EDDY_OK) return ts;
+    std::vector<int> cp(o->ns);
+    HIP_TRY(hipMemcpyAsync(cp.data(), o->sell_cplx, sizeof(int) * o->ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    t.sell_nnz_real = 0;
+    for (int64_t q = 0; q < o->ns; ++q)
+      if (!cp[q]) t.sell_nnz_real += o->sell_nz_h[q];
     o->tuned = true;
   }
   o->assembled = true;
@@ -938,7 +955,8 @@ eddy_status run_gmres(eddy_op* o, SolveWs& W, Inner<T, VT>& I, const eddy_solve_
       launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, I.sval, o->ne, gauge_op ? o->wrowptr : nullptr,
                   o->wcol, o->wval, o->tvec, (const T*)zj, nullptr, I.w, s,
                   std::is_same<T, float2>::value ? o->tune.spmv_grid_c64 : o->tune.spmv_grid_c128,
-                  std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128, o->xcd_groups);
+                  std::is_same<T, float2>::value ? o->tune.spmv_sched_c64 : o->tune.spmv_sched_c128, o->xcd_groups,
+                  o->sell_cplx);
       if (prof) (void)hipEventRecord(ev[3], s);
       launch_mdot2(n, (const VT*)I.V, ld, j, (const VT*)vj, (const T*)I.w, W.part, s);
       launch_reduce_cols(2 * j + 2, nparts, W.part, W.dots, s);

@@ -46,11 +46,11 @@ template <class T>
 void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, const T* sval, int64_t ne,
                  const int* wrowptr, const int* wcol, const double* wval, const double2* t, const T* x,
                  const double2* b, T* y, hipStream_t st, int grid = 0, int schedule = 0,
-                 const int* xcd_groups = nullptr);
+                 const int* xcd_groups = nullptr, const int* scplx = nullptr);
 // workgroups of an uncapped SpMV launch over ns slices
 int spmv_full_grid(int64_t ns);
-void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2* sval, float2* sval32,
-                        hipStream_t st);
+void launch_sell_gather(int64_t tot, int64_t ns, const int* sptr, const int* src, const double2* val, double2* sval,
+                        float2* sval32, int* scplx, hipStream_t st);
 // MT: storage of the inverses, T or (with T = float2) packed complex half
 // (uint32_t); RT: storage of r (T, or hbasis with T = float2)
 template <class T, class MT, class RT>

@@ -698,7 +698,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* _
                                                         const int* __restrict__ srow, const int* __restrict__ scol,
                                                         const T* __restrict__ sval, const T* __restrict__ x,
                                                         const double2* __restrict__ b, T* __restrict__ y,
-                                                        int schedule, const int* __restrict__ xcd_groups) {
+                                                        int schedule, const int* __restrict__ xcd_groups,
+                                                        const int* __restrict__ scplx) {
   static_assert(kSellC == 64, "one wavefront per slice");
   constexpr int kGroup = kThreads / 64;
   const int l = threadIdx.x & 63;
@@ -727,8 +728,21 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* _
     // column loads, then gathers, unrolled as deep as occupancy allows
     // (measured: complex64 8 deep, 7 waves per SIMD; complex128 4 deep)
     if constexpr (sizeof(T) == 8) {
+      if (scplx && !scplx[s]) {
+        // real slice (complex64 copy only): the same products with a zero
+        // imaginary part, 4-byte values
+        const float* __restrict__ vr = reinterpret_cast<const float*>(sval) + 2 * (int64_t)p0 + l;
 #pragma unroll 8
-      for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+        for (int j = 0; j < w; ++j) {
+          const float a = ld_stream(vr + j * kSellC);
+          const T xv = x[ld_stream(c + j * kSellC)];
+          acc.x = fmaf(a, xv.x, acc.x);
+          acc.y = fmaf(a, xv.y, acc.y);
+        }
+      } else {
+#pragma unroll 8
+        for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+      }
     } else {
 #pragma unroll 4
       for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
@@ -760,14 +774,40 @@ __global__ __launch_bounds__(kThreads) void k_gauge_add(int64_t ne, const int* _
 
 // Values of the sliced ELL copy from the CSR values (padding = 0).
 __global__ __launch_bounds__(kThreads) void k_sell_gather(int64_t tot, const int* __restrict__ src,
-                                                          const double2* __restrict__ val, double2* __restrict__ sval,
-                                                          float2* __restrict__ sval32) {
+                                                          const double2* __restrict__ val, double2* __restrict__ sval) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= tot) return;
   const int p = src[i];
-  const double2 v = p >= 0 ? val[p] : make_double2(0.0, 0.0);
-  sval[i] = v;
-  sval32[i] = make_float2((float)v.x, (float)v.y);
+  sval[i] = p >= 0 ? val[p] : make_double2(0.0, 0.0);
+}
+
+// The complex64 copy, one wavefront per slice.  A slice whose complex64
+// values all have a zero imaginary part is stored real: entry j of lane l as
+// the float at 2 sptr[s] + 64 j + l (the first half of the slice's range),
+// and scplx[s] = 0; otherwise as complex64 at sptr[s] + 64 j + l, scplx[s] = 1.
+__global__ __launch_bounds__(kThreads) void k_sell_c64(int64_t ns, const int* __restrict__ sptr,
+                                                       const int* __restrict__ src, const double2* __restrict__ val,
+                                                       float2* __restrict__ sval32, int* __restrict__ scplx) {
+  const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int l = threadIdx.x & 63;
+  if (s >= ns) return;              // uniform over the wavefront
+  const int p0 = sptr[s], w = (sptr[s + 1] - p0) / kSellC;
+  bool im = false;
+  for (int j = 0; j < w; ++j) {
+    const int p = src[p0 + j * kSellC + l];
+    if (p >= 0 && (float)val[p].y != 0.0f) im = true;
+  }
+  const bool cplx = __ballot(im) != 0;
+  if (l == 0) scplx[s] = cplx ? 1 : 0;
+  float* __restrict__ re = reinterpret_cast<float*>(sval32) + 2 * (int64_t)p0 + l;
+  for (int j = 0; j < w; ++j) {
+    const int p = src[p0 + j * kSellC + l];
+    const double2 v = p >= 0 ? val[p] : make_double2(0.0, 0.0);
+    if (cplx)
+      sval32[p0 + j * kSellC + l] = make_float2((float)v.x, (float)v.y);
+    else
+      re[j * kSellC] = (float)v.x;
+  }
 }
 
 // z_I = Minv_I r_I, one 64-lane wavefront per block, 4 blocks per workgroup;
@@ -2142,18 +2182,21 @@ void launch_wt(int64_t nv, const int* wtrowptr, const int* wtcol, const double* 
 template <class T>
 void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, const T* sval, int64_t ne,
                  const int* wrowptr, const int* wcol, const double* wval, const double2* t, const T* x,
-                 const double2* b, T* y, hipStream_t st, int grid, int schedule, const int* xcd_groups) {
+                 const double2* b, T* y, hipStream_t st, int grid, int schedule, const int* xcd_groups,
+                 const int* scplx) {
   const unsigned full = blocks_for(ns * kSellC);
   unsigned g = grid > 0 && (unsigned)grid < full ? (unsigned)grid : full;
   if (schedule && (g < (unsigned)kXcds || !xcd_groups)) schedule = 0;
-  k_spmv_sell<T><<<g, kThreads, 0, st>>>(ns, sptr, srow, scol, sval, x, b, y, schedule, xcd_groups);
+  k_spmv_sell<T><<<g, kThreads, 0, st>>>(ns, sptr, srow, scol, sval, x, b, y, schedule, xcd_groups,
+                                         sizeof(T) == 8 ? scplx : nullptr);
   if (wrowptr)
     k_gauge_add<T><<<blocks_for(ne * kLanes), kThreads, 0, st>>>(ne, wrowptr, wcol, wval, t, b ? -1.0 : 1.0, y);
 }
 int spmv_full_grid(int64_t ns) { return (int)blocks_for(ns * kSellC); }
-void launch_sell_gather(int64_t tot, const int* src, const double2* val, double2* sval, float2* sval32,
-                        hipStream_t st) {
-  k_sell_gather<<<blocks_for(tot), kThreads, 0, st>>>(tot, src, val, sval, sval32);
+void launch_sell_gather(int64_t tot, int64_t ns, const int* sptr, const int* src, const double2* val, double2* sval,
+                        float2* sval32, int* scplx, hipStream_t st) {
+  k_sell_gather<<<blocks_for(tot), kThreads, 0, st>>>(tot, src, val, sval);
+  k_sell_c64<<<blocks_for(ns * kSellC), kThreads, 0, st>>>(ns, sptr, src, val, sval32, scplx);
 }
 template <class T, class MT, class RT>
 void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const RT* r, T* z,
@@ -2370,7 +2413,7 @@ void launch_to_c64(int64_t n, const double2* in, float2* out, hipStream_t st) {
 #define EDDY_INST(T)                                                                                              \
   template void launch_spmv<T>(int64_t, const int*, const int*, const int*, const T*, int64_t, const int*,       \
                                const int*, const double*, const double2*, const T*, const double2*, T*,          \
-                               hipStream_t, int, int, const int*);                                               \
+                               hipStream_t, int, int, const int*, const int*);                                   \
   template void launch_block_apply<T, T, T>(int64_t, const int*, const int*, const T*, const T*, T*, hipStream_t); \
   template void launch_mdot<T>(int64_t, const T*, int64_t, int, const T*, double2*, hipStream_t, int, const int*); \
   template void launch_norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                \

@@ -119,15 +119,25 @@ int find_root(std::vector<int32_t>& p, int32_t x) {
 
 // Sliced ELL layout of the CSR pattern (see internal.h).  Sorting by length
 // inside a window keeps the padding small (rows of an edge matrix have a few
-// distinct lengths) while the row permutation stays local.
+// distinct lengths) while the row permutation stays local.  Inside a window
+// the rows that can hold complex values (V rows and the rows that couple to
+// V: edges of conducting tetrahedra and of impedance triangles) come first,
+// so that the other slices hold only real values (the SpMV then reads 4-byte
+// values there; which slices are real is decided from the values at
+// assembly).
 eddy_status build_sell(eddy_mesh* m) {
-  const int64_t n = m->ndof();
+  const int64_t n = m->ndof(), ne = m->ne;
   const int64_t ns = (n + kSellC - 1) / kSellC;
   std::vector<int32_t> order(ns * kSellC, -1);
+  std::vector<uint8_t> cplx(n, 0);
+  for (int64_t r = 0; r < n; ++r)
+    cplx[r] = r >= ne || (m->rowptr[r + 1] > m->rowptr[r] && *std::max_element(m->col.begin() + m->rowptr[r],
+                                                                                m->col.begin() + m->rowptr[r + 1]) >= ne);
   for (int64_t w0 = 0; w0 < n; w0 += kSellWindow) {
     const int64_t w1 = std::min<int64_t>(n, w0 + kSellWindow);
     std::iota(order.begin() + w0, order.begin() + w1, (int32_t)w0);
     std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int32_t a, int32_t b) {
+      if (cplx[a] != cplx[b]) return cplx[a] > cplx[b];
       return m->rowptr[a + 1] - m->rowptr[a] > m->rowptr[b + 1] - m->rowptr[b];
     });
   }

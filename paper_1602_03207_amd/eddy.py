@@ -35,7 +35,8 @@ class _Tuning(C.Structure):
     _fields_ = [("spmv_grid_full", C.c_int32), ("spmv_grid_c128", C.c_int32), ("spmv_grid_c64", C.c_int32),
                 ("spmv_sched_c128", C.c_int32), ("spmv_sched_c64", C.c_int32),
                 ("spmv_us_c128", C.c_float), ("spmv_us_c64", C.c_float),
-                ("spmv_us_sched_c128", C.c_float * 2), ("spmv_us_sched_c64", C.c_float * 2)]
+                ("spmv_us_sched_c128", C.c_float * 2), ("spmv_us_sched_c64", C.c_float * 2),
+                ("sell_nnz_real", C.c_int64)]
 
 
 class _Report(C.Structure):
