@@ -94,8 +94,8 @@ def workload(name):
 def spmv_bytes(M, op, vb=16, gauge=False, nnz_real=0):
     """Algorithmic bytes of one k_spmv launch: values + col + rowptr + x once + y;
     vb = bytes per complex value (16 complex128, 8 complex64); nnz_real
-    nonzeros sit in real slices of the complex64 copy (4-byte values); the
-    gauged variant also streams W~ and reads t."""
+    nonzeros sit in real slices (values of vb / 2 bytes); the gauged variant
+    also streams W~ and reads t."""
     n, ne, nv = op.ndof, op.ne, op.nv
     b = (vb + 4) * M.nnz - (vb // 2) * nnz_real + 4 * (n + 1) + 2 * vb * n
     if gauge:
@@ -250,7 +250,7 @@ def main():
         mb = 4 if prec == "mixed16" else vb
         kb = {"block_apply": block_apply_bytes(M, op, args.block, vb, mb), "gauge_wt": wt_bytes(M, op),
               "spmv": spmv_bytes(M, op, vb, gauge=reps[-1][0].gauge_in_operator,
-                                 nnz_real=op.tuning()["sell_nnz_real"] if vb == 8 else 0)}
+                                 nnz_real=op.tuning()["sell_nnz_real"])}
         kernels = {}
         for name, (ms, cnt) in prof.items():
             avg = ms / max(cnt, 1)

@@ -128,8 +128,9 @@ typedef struct {
   float spmv_us_c64;
   float spmv_us_sched_c128[2];  /* best time of each schedule                          */
   float spmv_us_sched_c64[2];
-  int64_t sell_nnz_real;    /* nonzeros in the sliced-ELL slices whose complex64 values */
-                            /* are all real (stored as 4-byte values for that SpMV)    */
+  int64_t sell_nnz_real;    /* nonzeros in the sliced-ELL slices whose values are all  */
+                            /* real (stored real: 8-byte and 4-byte values in the     */
+                            /* complex128 and complex64 copies)                       */
 } eddy_tuning;
 
 /* ---- mesh (host) -------------------------------------------------------

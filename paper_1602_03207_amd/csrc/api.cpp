@@ -73,7 +73,7 @@ struct eddy_op {
   int *d0ptr, *d0list, *lcptr, *lclist, *rptr, *rlist;
   int *blk_ptr, *blk_dofs, *blk_of, *loc_of;
   int *sell_ptr, *sell_row, *sell_col, *sell_src;
-  int* sell_cplx;                  // per slice: 1 complex64 values, 0 real (4-byte values)
+  int* sell_cplx;                  // per slice: 1 complex values, 0 real (values stored real)
   std::vector<int64_t> sell_nz_h;  // per slice: stored nonzeros (padding excluded)
   int *lrowptr, *lcol;          // L = W^T G pattern (Coulomb projection)
   int* xcd_groups;              // SpMV schedule 1: group ranges of equal stored entries per XCD
@@ -307,7 +307,7 @@ void op_spmv(const eddy_op* o, const double2* x, const double2* b, double2* y, d
              bool gauge = true) {
   if (gauge) launch_wt(o->nv, o->wtrowptr, o->wtcol, o->wtval, o->d0tau, x, t, st);
   launch_spmv(o->ns, o->sell_ptr, o->sell_row, o->sell_col, o->sval, o->ne, gauge ? o->wrowptr : nullptr, o->wcol,
-              o->wval, t, x, b, y, st, o->tune.spmv_grid_c128, o->tune.spmv_sched_c128, o->xcd_groups);
+              o->wval, t, x, b, y, st, o->tune.spmv_grid_c128, o->tune.spmv_sched_c128, o->xcd_groups, o->sell_cplx);
 }
 
 }  // namespace

@@ -54,6 +54,7 @@ typedef double v2d_t __attribute__((ext_vector_type(2)));
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ double2 ld_stream(const double2* p) {
   const v2d_t v = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(p));
   return make_double2(v.x, v.y);

@@ -729,8 +729,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* _
     // (measured: complex64 8 deep, 7 waves per SIMD; complex128 4 deep)
     if constexpr (sizeof(T) == 8) {
       if (scplx && !scplx[s]) {
-        // real slice (complex64 copy only): the same products with a zero
-        // imaginary part, 4-byte values
+        // real slice: the same products with a zero imaginary part, values
+        // of half the size
         const float* __restrict__ vr = reinterpret_cast<const float*>(sval) + 2 * (int64_t)p0 + l;
 #pragma unroll 8
         for (int j = 0; j < w; ++j) {
@@ -744,8 +744,19 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sell(int64_t ns, const int* _
         for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
       }
     } else {
+      if (scplx && !scplx[s]) {
+        const double* __restrict__ vr = reinterpret_cast<const double*>(sval) + 2 * (int64_t)p0 + l;
 #pragma unroll 4
-      for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+        for (int j = 0; j < w; ++j) {
+          const double a = ld_stream(vr + j * kSellC);
+          const T xv = x[ld_stream(c + j * kSellC)];
+          acc.x = fma(a, xv.x, acc.x);
+          acc.y = fma(a, xv.y, acc.y);
+        }
+      } else {
+#pragma unroll 4
+        for (int j = 0; j < w; ++j) acc = cfmaT(ld_stream(v + j * kSellC), x[ld_stream(c + j * kSellC)], acc);
+      }
     }
     if (row >= 0) y[row] = b ? st2<T>(csub(b[row], ld2(acc))) : acc;
   }
@@ -773,21 +784,16 @@ __global__ __launch_bounds__(kThreads) void k_gauge_add(int64_t ne, const int* _
 }
 
 // Values of the sliced ELL copy from the CSR values (padding = 0).
-__global__ __launch_bounds__(kThreads) void k_sell_gather(int64_t tot, const int* __restrict__ src,
-                                                          const double2* __restrict__ val, double2* __restrict__ sval) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= tot) return;
-  const int p = src[i];
-  sval[i] = p >= 0 ? val[p] : make_double2(0.0, 0.0);
-}
-
-// The complex64 copy, one wavefront per slice.  A slice whose complex64
-// values all have a zero imaginary part is stored real: entry j of lane l as
-// the float at 2 sptr[s] + 64 j + l (the first half of the slice's range),
-// and scplx[s] = 0; otherwise as complex64 at sptr[s] + 64 j + l, scplx[s] = 1.
-__global__ __launch_bounds__(kThreads) void k_sell_c64(int64_t ns, const int* __restrict__ sptr,
-                                                       const int* __restrict__ src, const double2* __restrict__ val,
-                                                       float2* __restrict__ sval32, int* __restrict__ scplx) {
+// Values of the sliced ELL copies from the CSR values (padding = 0), one
+// wavefront per slice.  A slice whose values all have a zero imaginary part
+// is stored real in both copies: entry j of lane l as the double (complex128
+// copy) or float (complex64 copy) at 2 sptr[s] + 64 j + l, the first half of
+// the slice's range, and scplx[s] = 0; otherwise complex at sptr[s] + 64 j + l
+// and scplx[s] = 1.
+__global__ __launch_bounds__(kThreads) void k_sell_values(int64_t ns, const int* __restrict__ sptr,
+                                                          const int* __restrict__ src, const double2* __restrict__ val,
+                                                          double2* __restrict__ sval, float2* __restrict__ sval32,
+                                                          int* __restrict__ scplx) {
   const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int l = threadIdx.x & 63;
   if (s >= ns) return;              // uniform over the wavefront
@@ -795,18 +801,23 @@ __global__ __launch_bounds__(kThreads) void k_sell_c64(int64_t ns, const int* __
   bool im = false;
   for (int j = 0; j < w; ++j) {
     const int p = src[p0 + j * kSellC + l];
-    if (p >= 0 && (float)val[p].y != 0.0f) im = true;
+    if (p >= 0 && val[p].y != 0.0) im = true;
   }
   const bool cplx = __ballot(im) != 0;
   if (l == 0) scplx[s] = cplx ? 1 : 0;
-  float* __restrict__ re = reinterpret_cast<float*>(sval32) + 2 * (int64_t)p0 + l;
+  double* __restrict__ re = reinterpret_cast<double*>(sval) + 2 * (int64_t)p0 + l;
+  float* __restrict__ re32 = reinterpret_cast<float*>(sval32) + 2 * (int64_t)p0 + l;
   for (int j = 0; j < w; ++j) {
-    const int p = src[p0 + j * kSellC + l];
+    const int q = p0 + j * kSellC + l;
+    const int p = src[q];
     const double2 v = p >= 0 ? val[p] : make_double2(0.0, 0.0);
-    if (cplx)
-      sval32[p0 + j * kSellC + l] = make_float2((float)v.x, (float)v.y);
-    else
-      re[j * kSellC] = (float)v.x;
+    if (cplx) {
+      sval[q] = v;
+      sval32[q] = make_float2((float)v.x, (float)v.y);
+    } else {
+      re[j * kSellC] = v.x;
+      re32[j * kSellC] = (float)v.x;
+    }
   }
 }
 
@@ -2187,16 +2198,14 @@ void launch_spmv(int64_t ns, const int* sptr, const int* srow, const int* scol, 
   const unsigned full = blocks_for(ns * kSellC);
   unsigned g = grid > 0 && (unsigned)grid < full ? (unsigned)grid : full;
   if (schedule && (g < (unsigned)kXcds || !xcd_groups)) schedule = 0;
-  k_spmv_sell<T><<<g, kThreads, 0, st>>>(ns, sptr, srow, scol, sval, x, b, y, schedule, xcd_groups,
-                                         sizeof(T) == 8 ? scplx : nullptr);
+  k_spmv_sell<T><<<g, kThreads, 0, st>>>(ns, sptr, srow, scol, sval, x, b, y, schedule, xcd_groups, scplx);
   if (wrowptr)
     k_gauge_add<T><<<blocks_for(ne * kLanes), kThreads, 0, st>>>(ne, wrowptr, wcol, wval, t, b ? -1.0 : 1.0, y);
 }
 int spmv_full_grid(int64_t ns) { return (int)blocks_for(ns * kSellC); }
 void launch_sell_gather(int64_t tot, int64_t ns, const int* sptr, const int* src, const double2* val, double2* sval,
                         float2* sval32, int* scplx, hipStream_t st) {
-  k_sell_gather<<<blocks_for(tot), kThreads, 0, st>>>(tot, src, val, sval);
-  k_sell_c64<<<blocks_for(ns * kSellC), kThreads, 0, st>>>(ns, sptr, src, val, sval32, scplx);
+  k_sell_values<<<blocks_for(ns * kSellC), kThreads, 0, st>>>(ns, sptr, src, val, sval, sval32, scplx);
 }
 template <class T, class MT, class RT>
 void launch_block_apply(int64_t nb, const int* blk_ptr, const int* blk_dofs, const MT* minv, const RT* r, T* z,
