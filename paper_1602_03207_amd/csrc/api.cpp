@@ -1334,6 +1334,7 @@ eddy_status run_batched(eddy_op* o, const Groups& G, BatchWs& B, const eddy_solv
   };
   std::vector<int> done(nrhs, 0), run(nrhs), cyc(nrhs), kc(nrhs);
   std::vector<double> beta(bnorm), est((size_t)nrhs * (m + 1));
+  std::vector<char> at_max(nrhs, 0);   // reached max_iter inside a cycle
   for (int r = 0; r < nrhs; ++r) done[r] = bnorm[r] > 0 ? 0 : 1;
   HIP_TRY(hipMemcpyAsync(B.bnorm, bnorm.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
   const double2 zero2h[kMaxRestart + 2] = {};
@@ -1399,10 +1400,13 @@ eddy_status run_batched(eddy_op* o, const Groups& G, BatchWs& B, const eddy_solv
           }
         }
         if (run[r] && its[r] >= opts->max_iter) {
-          // mid-cycle the last step's column is not final: stop with the finished ones
+          // mid-cycle the last step's column is not final: stop with the
+          // finished ones, and end the solve at this cycle's end (its is one
+          // below max_iter now; another cycle would repeat the same cut)
           kc[r] = avail;
           its[r] -= (j + 1) - kc[r];
           run[r] = 0;
+          at_max[r] = 1;
           changed = true;
         }
         nrun += run[r];
@@ -1437,7 +1441,7 @@ eddy_status run_batched(eddy_op* o, const Groups& G, BatchWs& B, const eddy_solv
       beta[r] = nr[r];
       R[r].restarts++;
       R[r].relres = beta[r] / bnorm[r];
-      if (R[r].relres <= opts->tol || its[r] >= opts->max_iter) done[r] = 1;
+      if (R[r].relres <= opts->tol || its[r] >= opts->max_iter || at_max[r]) done[r] = 1;
       else if (R[r].breakdown && kc[r] < m) {
         // as in the single solve: a breakdown with an unconverged true
         // residual restarts while the cycle made progress

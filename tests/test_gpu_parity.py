@@ -367,6 +367,25 @@ def test_batched_solve_with_two_chunks(precision):
         assert np.linalg.norm(X[r].cpu().numpy() - xo) <= 1e-9 * np.linalg.norm(xo)
 
 
+def test_batched_solve_ends_at_max_iter_inside_a_cycle():
+    """A system that reaches max_iter one step into a cycle keeps the finished
+    columns and ends (it used to start the same one-step cycle again and
+    again).  restart 30, max_iter 31: the second cycle is cut after its
+    first step; the eager single solve stops at the same limit."""
+    m, s, op, _ = case("c1")
+    Js = [cube_current(m, seed) for seed in (0, 1)]
+    B = torch.stack([op.rhs_from_current(torch.from_numpy(J).cuda()) for J in Js])
+    for prec in ("fp64", "mixed16"):
+        X, reps = op.solve_batched(B.clone(), tol=1e-15, restart=30, max_iter=31, precision=prec)
+        for r in reps:
+            print(f"{prec}: iters {r.iters}, restarts {r.restarts}, relres {r.relres:.2e}")
+            assert not r.converged and 30 <= r.iters <= 31 and r.restarts <= 2
+        _, r1 = op.solve(B[0].clone(), tol=1e-15, restart=30, max_iter=31, precision=prec)
+        assert not r1.converged and r1.iters == 31
+        assert reps[0].relres < 1.0 and 0.2 * r1.relres <= reps[0].relres <= 5.0 * r1.relres
+        assert torch.isfinite(torch.view_as_real(X)).all()
+
+
 def test_batched_solve_rejects_non_solenoidal_and_handles_zero_rhs():
     from paper_1602_03207_amd import eddy
     m, s, op, J = case("c1")
