@@ -794,10 +794,10 @@ eddy_status finish_solution(eddy_op* o, const ProjBufs& P, const double2* xt, co
       int cur = 0;
       const int kMaxCg = 20000;
       for (int ci = 1; ci <= kMaxCg; ++ci) {
-        launch_lap_spmv_dot(nv, o->lrowptr, o->lcol, o->lval, P.cp, P.cq, P.part, P.cs + 2, s);
-        launch_cg_update(nv, P.cs + cur, P.cs + 2, P.cp, P.cq, o->ldiag, P.psi, P.cr, P.cz, P.part,
-                         P.cs + (1 - cur), s);
-        launch_cg_dir(nv, P.cs + (1 - cur), P.cs + cur, P.cz, P.cp, s);
+        // the p^H q partials in part[0, kRedBlocks), the r^H z partials after them
+        launch_lap_spmv_dot(nv, o->lrowptr, o->lcol, o->lval, P.cp, P.cq, P.part, s);
+        launch_cg_update(nv, P.cs + cur, P.part, P.cp, P.cq, o->ldiag, P.psi, P.cr, P.cz, P.part + kRedBlocks, s);
+        launch_cg_dir(nv, P.part + kRedBlocks, P.cs + cur, P.cs + (1 - cur), P.cz, P.cp, s);
         cur = 1 - cur;
         R.cg_iters = ci;
         if (ci % 25 == 0 || ci == kMaxCg) {
@@ -1232,7 +1232,10 @@ size_t carve_batch(BatchWs* B, void* base, const eddy_op* o, int nrhs, int m, in
   B->bt = c.take<double2>((int64_t)nrhs * ld);
   B->w64 = c.take<double2>((int64_t)nrhs * ld);
   const int64_t np = mdot_parts(n > nv ? n : nv);
-  B->part = c.take<double2>((int64_t)nrhs * std::max<int64_t>(np * (m + 2), (int64_t)mdot2_parts(n) * (2 * m + 2)));
+  // also the projection CG's two sets of kRedBlocks partials (P.part)
+  B->part = c.take<double2>(std::max<int64_t>((int64_t)nrhs * std::max<int64_t>(np * (m + 2),
+                                                                                (int64_t)mdot2_parts(n) * (2 * m + 2)),
+                                              2 * kRedBlocks));
   B->Hraw = c.take<double2>((int64_t)nrhs * (m + 1) * m);
   B->dots = c.take<double2>((int64_t)nrhs * (2 * kMaxRestart + 4));
   B->coef = c.take<double2>((int64_t)nrhs * (2 * kMaxRestart + 4));

@@ -199,14 +199,14 @@ void launch_lap_diag(int64_t nv, const int* wtrowptr, const int* wtcol, const do
 // partial: kRedBlocks double2
 void launch_lap_assemble(int64_t nv, const int* wtrowptr, const int* wtcol, const double* wtval, const int* edges,
                          const double* s, const int* lrowptr, const int* lcol, double* lval, hipStream_t st);
+// projection CG: partial sums in kRedBlocks slots, summed by the consumer
 void launch_lap_spmv_dot(int64_t nv, const int* lrowptr, const int* lcol, const double* lval, const double2* p,
-                         double2* q, double2* partial, double2* pq, hipStream_t st);
-void launch_cg_update(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q,
-                      const double* diag, double2* psi, double2* r, double2* z, double2* partial, double2* rz_new,
-                      hipStream_t st);
+                         double2* q, double2* partial, hipStream_t st);
+void launch_cg_update(int64_t n, const double2* rz, const double2* pq_part, const double2* p, const double2* q,
+                      const double* diag, double2* psi, double2* r, double2* z, double2* partial, hipStream_t st);
 void launch_jacobi(int64_t n, const double2* r, const double* diag, double2* z, hipStream_t st);
-void launch_cg_dir(int64_t n, const double2* rz_new, const double2* rz_old, const double2* z, double2* p,
-                   hipStream_t st);
+void launch_cg_dir(int64_t n, const double2* rz_part, const double2* rz_old, double2* rz_new, const double2* z,
+                   double2* p, hipStream_t st);
 void launch_project(int64_t ne, int64_t nc, const int* edges, const int* cond_nodes, const double2* psi, double omega,
                     double2* x, hipStream_t st);
 // Defect-region volume form of the impedance change for one defect-configuration

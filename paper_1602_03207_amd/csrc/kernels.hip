@@ -623,14 +623,22 @@ __global__ __launch_bounds__(kThreads) void k_lap_spmv_dot(int64_t nv, const int
 }
 
 // Projection CG, fused: alpha = rz / pq; psi += alpha p; r -= alpha q;
-// z = r / diag; per-block partial sums of r^H z.
+// z = r / diag; per-block partial sums of r^H z.  pq is summed here from the
+// kRedBlocks partials of k_lap_spmv_dot, in the fixed order of k_reduce_cols.
 __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t n, const double2* __restrict__ rz,
-                                                        const double2* __restrict__ pq, const double2* __restrict__ p,
+                                                        const double2* __restrict__ pq_part,
+                                                        const double2* __restrict__ p,
                                                         const double2* __restrict__ q, const double* __restrict__ diag,
                                                         double2* __restrict__ psi, double2* __restrict__ r,
                                                         double2* __restrict__ z, double2* __restrict__ partial) {
   __shared__ double sh[4];
-  const double den = pq[0].x;
+  __shared__ double den_s;
+  double d = 0.0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) d += pq_part[b].x;
+  d = block_sum(d, sh);
+  if (threadIdx.x == 0) den_s = d;
+  __syncthreads();
+  const double den = den_s;
   const double a = den != 0.0 ? rz[0].x / den : 0.0;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -655,14 +663,27 @@ __global__ __launch_bounds__(kThreads) void k_jacobi(int64_t n, const double2* _
   z[i] = make_double2(r[i].x * f, r[i].y * f);
 }
 
-// p = z + (rz_new / rz_old) p
-__global__ __launch_bounds__(kThreads) void k_cg_dir(int64_t n, const double2* __restrict__ rz_new,
+// p = z + (rz_new / rz_old) p, with rz_new summed here from the kRedBlocks
+// partials of k_cg_update (the fixed order of k_reduce_cols); workgroup 0
+// stores it for the next iteration's k_cg_update.
+__global__ __launch_bounds__(kThreads) void k_cg_dir(int64_t n, const double2* __restrict__ rz_part,
                                                      const double2* __restrict__ rz_old,
+                                                     double2* __restrict__ rz_new,
                                                      const double2* __restrict__ z, double2* __restrict__ p) {
+  __shared__ double sh[4];
+  __shared__ double num_s;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x) a += rz_part[b].x;
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) {
+    num_s = a;
+    if (blockIdx.x == 0) rz_new[0] = make_double2(a, 0.0);
+  }
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double den = rz_old[0].x;
-  const double bta = den != 0.0 ? rz_new[0].x / den : 0.0;
+  const double bta = den != 0.0 ? num_s / den : 0.0;
   p[i] = rfma(bta, p[i], z[i]);
 }
 
@@ -2571,22 +2592,19 @@ void launch_lap_assemble(int64_t nv, const int* wtrowptr, const int* wtcol, cons
   k_lap_assemble<<<blocks_for(nv), kThreads, 0, st>>>(nv, wtrowptr, wtcol, wtval, edges, s, lrowptr, lcol, lval);
 }
 void launch_lap_spmv_dot(int64_t nv, const int* lrowptr, const int* lcol, const double* lval, const double2* p,
-                         double2* q, double2* partial, double2* pq, hipStream_t st) {
+                         double2* q, double2* partial, hipStream_t st) {
   k_lap_spmv_dot<<<kRedBlocks, kThreads, 0, st>>>(nv, lrowptr, lcol, lval, p, q, partial);
-  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, kRedBlocks, pq, nullptr, 0, 0, nullptr);
 }
-void launch_cg_update(int64_t n, const double2* rz, const double2* pq, const double2* p, const double2* q,
-                      const double* diag, double2* psi, double2* r, double2* z, double2* partial, double2* rz_new,
-                      hipStream_t st) {
-  k_cg_update<<<kRedBlocks, kThreads, 0, st>>>(n, rz, pq, p, q, diag, psi, r, z, partial);
-  k_reduce_cols<<<1, kThreads, 0, st>>>(partial, kRedBlocks, rz_new, nullptr, 0, 0, nullptr);
+void launch_cg_update(int64_t n, const double2* rz, const double2* pq_part, const double2* p, const double2* q,
+                      const double* diag, double2* psi, double2* r, double2* z, double2* partial, hipStream_t st) {
+  k_cg_update<<<kRedBlocks, kThreads, 0, st>>>(n, rz, pq_part, p, q, diag, psi, r, z, partial);
 }
 void launch_jacobi(int64_t n, const double2* r, const double* diag, double2* z, hipStream_t st) {
   k_jacobi<<<blocks_for(n), kThreads, 0, st>>>(n, r, diag, z);
 }
-void launch_cg_dir(int64_t n, const double2* rz_new, const double2* rz_old, const double2* z, double2* p,
-                   hipStream_t st) {
-  k_cg_dir<<<blocks_for(n), kThreads, 0, st>>>(n, rz_new, rz_old, z, p);
+void launch_cg_dir(int64_t n, const double2* rz_part, const double2* rz_old, double2* rz_new, const double2* z,
+                   double2* p, hipStream_t st) {
+  k_cg_dir<<<blocks_for(n), kThreads, 0, st>>>(n, rz_part, rz_old, rz_new, z, p);
 }
 void launch_project(int64_t ne, int64_t nc, const int* edges, const int* cond_nodes, const double2* psi, double omega,
                     double2* x, hipStream_t st) {
