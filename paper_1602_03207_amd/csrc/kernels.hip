@@ -1155,6 +1155,7 @@ __global__ __launch_bounds__(kThreads) void k_scale_by_inv(int64_t n, const Ti* 
 // formed by every workgroup in k_norm2_final's order (so the same value
 // everywhere, equal to k_norm2_final's); workgroup 0 stores ||w|| in
 // out_norm.  Saves the dependent launch of k_norm2_final per Arnoldi step.
+constexpr int kScaleGroups = 2;
 template <class Ti, class To>
 __global__ __launch_bounds__(kThreads) void k_scale_by_partials(int64_t n, const Ti* __restrict__ w,
                                                                 const double* __restrict__ rpart,
@@ -1173,23 +1174,28 @@ __global__ __launch_bounds__(kThreads) void k_scale_by_partials(int64_t n, const
   __syncthreads();
   const double a = nrm_s;
   const double f = a > 0.0 ? 1.0 / a : 0.0;
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R;
-  if (i0 >= n) return;
-  if (vec && i0 + R <= n) {
-    constexpr int Gi = rows_of<Ti>::R, Go = rows_of<To>::R;
-    const double fr = f * basis_unscale<Ti>();
-    double2 x[R];
+  // kScaleGroups row groups per thread, a workgroup's width apart (the sum
+  // above is formed once per workgroup, so fewer workgroups form it fewer times)
 #pragma unroll
-    for (int g = 0; g < R; g += Gi) ld_rows(w + i0 + g, x + g);
+  for (int t = 0; t < kScaleGroups; ++t) {
+    const int64_t i0 = (((int64_t)blockIdx.x * kScaleGroups + t) * blockDim.x + threadIdx.x) * R;
+    if (i0 >= n) return;
+    if (vec && i0 + R <= n) {
+      constexpr int Gi = rows_of<Ti>::R, Go = rows_of<To>::R;
+      const double fr = f * basis_unscale<Ti>();
+      double2 x[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = make_double2(x[r].x * fr, x[r].y * fr);
+      for (int g = 0; g < R; g += Gi) ld_rows(w + i0 + g, x + g);
 #pragma unroll
-    for (int g = 0; g < R; g += Go) st_rows(v + i0 + g, x + g);
-    return;
-  }
-  for (int r = 0; r < R && i0 + r < n; ++r) {
-    const double2 x = ld2(w[i0 + r]);
-    v[i0 + r] = st2<To>(make_double2(x.x * f, x.y * f));
+      for (int r = 0; r < R; ++r) x[r] = make_double2(x[r].x * fr, x[r].y * fr);
+#pragma unroll
+      for (int g = 0; g < R; g += Go) st_rows(v + i0 + g, x + g);
+      continue;
+    }
+    for (int r = 0; r < R && i0 + r < n; ++r) {
+      const double2 x = ld2(w[i0 + r]);
+      v[i0 + r] = st2<To>(make_double2(x.x * f, x.y * f));
+    }
   }
 }
 
@@ -2339,8 +2345,8 @@ void launch_dcgs_update(int64_t n, const VT* V, int64_t ldv, int q, const double
 template <class Ti, class To>
 void launch_scale_by_partials(int64_t n, const Ti* w, const double* rpart, double* out_norm, To* v, hipStream_t st) {
   constexpr int R = scale_rows<Ti, To>();
-  k_scale_by_partials<Ti, To><<<blocks_for((n + R - 1) / R), kThreads, 0, st>>>(n, w, rpart, out_norm, v,
-                                                                                 vec_ok(R, w, v, 0, 0));
+  k_scale_by_partials<Ti, To><<<blocks_for((n + R - 1) / R, kThreads * kScaleGroups), kThreads, 0, st>>>(
+      n, w, rpart, out_norm, v, vec_ok(R, w, v, 0, 0));
 }
 template <class VT, class T>
 void launch_mdot2_b(int64_t n, const VT* V, int64_t ldv, int64_t vstride, int q, const VT* v, const T* w,
